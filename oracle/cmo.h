@@ -1,0 +1,106 @@
+/*
+ * cmo.h -- plain FP64 CPU oracle for batched cognitive-model simulation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can check the HIP path
+ * against a slow, obviously correct implementation.  No product code may
+ * load or call it.  It shares no code, header, table or constant with the
+ * HIP library: everything here is written out on its own from the method's
+ * definition (the Distill paper, Sec. 2.2 "Cognitive Model Execution" and its
+ * scheduling listing, Sec. 3.3 "Dynamic to Static Data Structure Conversion",
+ * Sec. 3.6 "Parallelism and GPU Acceleration", Sec. 4.4 "Clone detection"
+ * for the DDM/LCA mechanisms) plus the readings listed in the design doc.
+ *
+ * All pointers are HOST pointers.  The caller owns every buffer; outputs are
+ * fully overwritten (histograms and statistics are zeroed first).
+ */
+#ifndef CMO_H
+#define CMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* model kinds */
+enum { CMO_DDM = 0, CMO_LCA = 1, CMO_RNN = 2 };
+/* precision modes */
+enum { CMO_FP64 = 0, CMO_FP32_STEP = 1, CMO_BF16_PROJ = 2 };
+
+/* Parameter slots: string keys become fixed offsets (Sec. 3.3). */
+enum { CMO_DDM_DT = 0, CMO_DDM_DRIFT, CMO_DDM_NOISE, CMO_DDM_THRESH,
+       CMO_DDM_START, CMO_DDM_T0, CMO_DDM_NPARAM };
+enum { CMO_LCA_DT = 0, CMO_LCA_LEAK, CMO_LCA_COMP, CMO_LCA_NOISE,
+       CMO_LCA_THRESH, CMO_LCA_OFFSET, CMO_LCA_HID_GAIN, CMO_LCA_HID_BIAS,
+       CMO_LCA_NONNEG, CMO_LCA_T0, CMO_LCA_NPARAM };
+enum { CMO_RNN_DT = 0, CMO_RNN_NOISE, CMO_RNN_THRESH, CMO_RNN_INPUT_GAIN,
+       CMO_RNN_T0, CMO_RNN_NPARAM };
+
+/* statistics per setting */
+enum { CMO_ST_DEC0 = 0, CMO_ST_DEC1, CMO_ST_UNDEC, CMO_ST_CORRECT,
+       CMO_ST_SUMN0, CMO_ST_SUMN1, CMO_ST_SUMSQ0, CMO_ST_SUMSQ1,
+       CMO_ST_FLAGGED, CMO_NSTAT };
+
+/* Random stream ids (counter word 3). */
+#define CMO_STREAM_DRIVE 0x40000000u
+#define CMO_STREAM_TIE 0xFFFFFFFFu
+
+typedef struct {
+  int32_t kind, precision;
+  int32_t n_units;     /* DDM 1, LCA 2, RNN n (even, <= 1024) */
+  int32_t n_stimuli;   /* DDM 1, LCA 9, RNN 1 */
+  int32_t n_signals;   /* DDM 0/1 (drift), LCA 0/2 (cA,cB), RNN 0/1 (gain) */
+  const double *params;
+  int32_t n_params;
+  const double *weights; /* LCA: WA[4x3] WB[4x3] OA[2x4] OB[2x4]; RNN: W[nxn] R[2xn] */
+  int64_t n_weights;
+} cmo_model;
+
+typedef struct {
+  const double *grid;  /* [n_settings x n_signals] or NULL when n_signals==0 */
+  int64_t n_settings;
+  uint64_t trials;     /* per setting */
+  uint64_t seed;
+  uint32_t max_steps, n_bins;
+  double reward, cost; /* both 0: no score */
+  double flag_eps;
+} cmo_sweep;
+
+typedef struct {
+  uint64_t *hist;     /* [n_settings][2][n_bins] */
+  uint64_t *stats;    /* [n_settings][CMO_NSTAT] */
+  double *score;      /* [n_settings] or NULL */
+  int64_t *best;      /* [2] or NULL */
+  int8_t *run_choice; /* optional per-run dumps, [n_settings*trials] */
+  uint32_t *run_step;
+  uint8_t *run_flag;
+  double *run_state;  /* [runs][state width]: DDM 1, LCA 2, RNN 2+n */
+} cmo_result;
+
+/* Whole sweep.  Returns 0 on success, nonzero on invalid arguments. */
+int cmo_run(const cmo_model *m, const cmo_sweep *s, cmo_result *r, int n_threads);
+
+/* Building blocks exposed for pins. */
+void cmo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void cmo_normals64(const uint32_t w[4], double z[2]);
+void cmo_normals32(const uint32_t w[4], float z[2]);
+double cmo_ddm_update(double x, double a, double b, double z);
+void cmo_lca_update(const double x[2], const double in[2], double leak, double comp,
+                    double dt, double b, const double z[2], double out[2]);
+/* conflict-network drive I[stim][2] and correct response per stimulus */
+void cmo_conflict_drive(const double *weights, double gain, double bias, double offset,
+                        double cA, double cB, double drive[9][2]);
+void cmo_conflict_correct(const double *weights, double gain, double bias, int32_t correct[9]);
+/* one run's trajectory: state after each executed step, [steps][width];
+ * returns the number of executed steps, writes choice and flag. */
+uint32_t cmo_trajectory(const cmo_model *m, const cmo_sweep *s, int64_t setting,
+                        uint64_t trial, double *states, int8_t *choice, uint8_t *flag);
+/* round-to-nearest-even double -> float -> bfloat16 bits */
+uint16_t cmo_bf16_bits(double v);
+int cmo_state_width(const cmo_model *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
