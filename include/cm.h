@@ -1,0 +1,198 @@
+/*
+ * cm.h -- C ABI of libcm, batched simulation of stochastic cognitive models
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library runs many independent stochastic runs of one model across a
+ * grid of parameter or control settings, as in the grid evaluation of the
+ * Distill paper (arXiv 2110.15425, Sec. 3.6: every grid point is an
+ * independent evaluation with its own random stream), reduces them to
+ * outcome histograms and per-setting statistics (Sec. 2.1: modellers want
+ * outcome distributions across parameter settings) and scores the grid,
+ * picking the best allocation with a random tie-break (Sec. 2.1, Sec. 3.3).
+ *
+ * Data layout follows Sec. 3.3: read-only parameters are separated from
+ * per-run state (which never leaves the GPU's registers), inputs and
+ * outputs are flat arrays, and string keys become the enum offsets below.
+ *
+ * Conventions for every entry point:
+ *  - No C++ types and no exceptions cross the ABI.  Every call returns a
+ *    cm_status; on anything but CM_OK a message is available from
+ *    cm_last_error() (thread-local) and output contents are undefined.
+ *  - Arguments are validated in full before anything is enqueued: a
+ *    rejected call has launched nothing.
+ *  - The caller owns all memory.  "DEVICE" pointers are HIP device
+ *    allocations on the handle's device, 8-byte aligned; the workspace is
+ *    256-byte aligned.  "HOST" pointers are read during the call only.
+ *  - Launches are asynchronous on the caller's HIP stream and ordered on it;
+ *    buffers must stay alive until the stream has passed the launch.
+ *  - The library allocates no device memory on the launch path.
+ *
+ * Determinism: for a fixed model, sweep and precision every integer output
+ * is independent of launch geometry, tuning and batching: random numbers
+ * are keyed by (seed, setting, trial, step) and all reductions are integer
+ * additions.
+ */
+#ifndef CM_H
+#define CM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CM_ABI_VERSION 1u
+
+typedef struct cm_handle cm_handle;
+
+typedef enum {
+  CM_OK = 0,
+  CM_E_INVALID = 1,     /* an argument violates the contract */
+  CM_E_BUDGET = 2,      /* workspace too small / request exceeds the budget */
+  CM_E_DEVICE = 3,      /* a HIP call failed; cm_last_error() has its text */
+  CM_E_UNSUPPORTED = 4, /* valid, but this kind/precision combination is not built */
+  CM_E_BUSY = 5         /* the serving queue is full; retry after cm_poll */
+} cm_status;
+
+/* Mechanism families (the DDM and LCA of Sec. 4.4; the logistic transfer and
+ * weight-matrix projections of Sec. 3.4.2). */
+typedef enum {
+  CM_DDM = 0,          /* drift-diffusion, Euler-Maruyama, bounds +-theta */
+  CM_CONFLICT_LCA = 1, /* two-pathway logistic network -> 2-unit leaky competing accumulator */
+  CM_RATE_RNN = 2      /* n-unit logistic recurrent rate network with a 2-unit readout */
+} cm_kind;
+
+/* Arithmetic modes.  CM_FP64: everything in double.  CM_FP32_STEP: normals,
+ * drive and increments in float, accumulators and threshold tests in
+ * double.  CM_BF16_PROJ (rate network only): CM_FP32_STEP plus the
+ * recurrent projection on bf16 matrix cores with float accumulation. */
+typedef enum { CM_FP64 = 0, CM_FP32_STEP = 1, CM_BF16_PROJ = 2 } cm_precision;
+
+/* Parameter offsets into cm_model.params, one table per kind. */
+enum { CM_DDM_DT = 0, CM_DDM_DRIFT, CM_DDM_NOISE, CM_DDM_THRESH, CM_DDM_START,
+       CM_DDM_T0, CM_DDM_NPARAM };
+enum { CM_LCA_DT = 0, CM_LCA_LEAK, CM_LCA_COMP, CM_LCA_NOISE, CM_LCA_THRESH,
+       CM_LCA_OFFSET, CM_LCA_HID_GAIN, CM_LCA_HID_BIAS, CM_LCA_NONNEG, CM_LCA_T0,
+       CM_LCA_NPARAM };
+enum { CM_RNN_DT = 0, CM_RNN_NOISE, CM_RNN_THRESH, CM_RNN_INPUT_GAIN, CM_RNN_T0,
+       CM_RNN_NPARAM };
+
+/* Per-setting statistics, CM_NSTAT uint64 words per setting. */
+enum { CM_ST_DEC0 = 0, CM_ST_DEC1, CM_ST_UNDEC, CM_ST_CORRECT, CM_ST_SUMN0,
+       CM_ST_SUMN1, CM_ST_SUMSQ0, CM_ST_SUMSQ1, CM_ST_FLAGGED, CM_NSTAT };
+
+/*
+ * The model.
+ *  kind, precision  cm_kind, cm_precision.
+ *  n_units          DDM 1; conflict LCA 2; rate network n, even, 64 <= n <= 256,
+ *                   n a multiple of 64.
+ *  n_stimuli        DDM 1; conflict LCA 9 (pairs (a, b) of one-hot inputs,
+ *                   trial t uses stimulus t mod 9, as the trial loop of
+ *                   Sec. 2.2 cycles through its input list); rate network 1.
+ *  n_signals        signals per grid setting.  DDM 0 or 1 (overrides the
+ *                   drift); conflict LCA 0 or 2 (control gains c_A, c_B,
+ *                   1 when absent); rate network 0 or 1 (overrides the
+ *                   input gain).
+ *  params           HOST, n_params doubles in the kind's enum order.
+ *  weights          DEVICE, row-major blocks.  Conflict LCA: W_A[4x3],
+ *                   W_B[4x3], O_A[2x4], O_B[2x4] (40 doubles).  Rate
+ *                   network: W[n x n] then R[2 x n].  DDM: unused (NULL).
+ */
+typedef struct {
+  uint32_t abi_version; /* CM_ABI_VERSION */
+  uint32_t kind, precision, n_units, n_stimuli, n_signals;
+  const double *params;
+  uint32_t n_params;
+  const double *weights;
+  uint64_t n_weights;
+} cm_model;
+
+/*
+ * The sweep: n_settings grid points x trials runs each.
+ *  grid       DEVICE [n_settings x n_signals] doubles, NULL if n_signals == 0.
+ *  trials     runs per setting, 1 <= trials < 2^31.
+ *  seed       64-bit key of every random stream.
+ *  max_steps  step cap N >= 1; a run that has not crossed by step N is
+ *             undecided (choice -1).
+ *  n_bins     histogram bins B, 1 <= B <= N; a run deciding at step n goes
+ *             to bin floor((n-1) B / N).
+ *  reward, cost  score[s] = reward * correct[s]/trials - cost * sum_k c_k^2;
+ *             both 0: no score.
+ *  flag_eps   a run is flagged when a compared quantity came within this
+ *             distance of its threshold (or, at a decision, the two
+ *             accumulators within it of each other).
+ */
+typedef struct {
+  const double *grid;
+  uint64_t n_settings;
+  uint64_t trials, seed;
+  uint32_t max_steps, n_bins;
+  double reward, cost;
+  double flag_eps;
+} cm_sweep;
+
+/*
+ * Outputs, all DEVICE, caller-allocated; the library zero-fills them.
+ *  hist     [n_settings][2][n_bins] uint64: decided runs per choice and bin.
+ *  stats    [n_settings][CM_NSTAT] uint64.
+ *  score    [n_settings] double, or NULL (required when reward/cost != 0).
+ *  best     [2] int64 {argmax setting, number of tied settings}, or NULL.
+ *  run_*    optional per-run dumps indexed setting * trials + trial:
+ *           choice (-1 undecided), decision step, flag, final state
+ *           (DDM x; LCA x0 x1; rate network y0 y1 then x[n]).
+ */
+typedef struct {
+  uint64_t *hist;
+  uint64_t *stats;
+  double *score;
+  int64_t *best;
+  int8_t *run_choice;
+  uint32_t *run_step;
+  uint8_t *run_flag;
+  double *run_state;
+} cm_result;
+
+/* Launch-shape knobs; 0 in a field means "let the library choose".
+ *  block          threads per workgroup (64..1024, multiple of 64).
+ *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane.
+ *  steps_per_sync lane-per-run kernels: steps between refills of finished
+ *                 lanes (1..64).
+ *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64). */
+typedef struct {
+  uint32_t block, runs_per_lane, steps_per_sync, tile_rows;
+} cm_tuning;
+
+/* Pure host checks of a model/sweep pair; touches no device. */
+cm_status cm_validate(const cm_model *model, const cm_sweep *sweep);
+
+/* Workspace bytes a launch of this model/sweep needs (host only). */
+cm_status cm_workspace_bytes(const cm_model *model, const cm_sweep *sweep, uint64_t *bytes);
+
+/* Handle bound to one HIP device: holds tuning and device properties. */
+cm_status cm_create(int device_ordinal, cm_handle **out);
+cm_status cm_destroy(cm_handle *h);
+cm_status cm_set_tuning(cm_handle *h, uint32_t kind, uint32_t precision, const cm_tuning *t);
+cm_status cm_get_tuning(cm_handle *h, uint32_t kind, uint32_t precision, cm_tuning *t);
+
+/* One sweep, stream-ordered on hip_stream (a hipStream_t, NULL = default).
+ * Enqueues: output zero-fill, drive precompute (conflict LCA), the
+ * simulation kernel, the score/argmax kernel when scoring is requested. */
+cm_status cm_launch(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
+                    const cm_result *result, void *workspace, uint64_t workspace_bytes,
+                    void *hip_stream);
+
+/* Kernel timing.  While enabled, every cm_launch brackets its simulation
+ * kernel with a pair of HIP events on the launch stream.  cm_profile_read
+ * waits for the recorded events, returns the summed kernel time in
+ * milliseconds and the number of timed launches since profiling was
+ * enabled, and keeps profiling on.  Enabling again resets the totals. */
+cm_status cm_profile(cm_handle *h, int enable);
+cm_status cm_profile_read(cm_handle *h, double *sim_ms, uint64_t *launches);
+
+/* Text of the last failure on this thread ("" if none). */
+const char *cm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

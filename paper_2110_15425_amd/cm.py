@@ -1,0 +1,255 @@
+"""Python binding of libcm (``include/cm.h``): argument marshalling only.
+
+Every step of a sweep runs in libcm's HIP kernels.  PyTorch provides device
+memory and the stream: buffers are ``torch`` CUDA tensors whose data
+pointers go through the C ABI, and launches are enqueued on
+``torch.cuda.current_stream()``.  If ``libcm.so`` is missing the binding
+raises; there is no fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcm.so")
+
+ABI_VERSION = 1
+OK, E_INVALID, E_BUDGET, E_DEVICE, E_UNSUPPORTED, E_BUSY = range(6)
+STATUS_NAMES = {0: "CM_OK", 1: "CM_E_INVALID", 2: "CM_E_BUDGET", 3: "CM_E_DEVICE",
+                4: "CM_E_UNSUPPORTED", 5: "CM_E_BUSY"}
+NSTAT = 9
+ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1=7, flagged=8)
+
+# every symbol include/cm.h declares
+EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
+           "cm_get_tuning", "cm_launch", "cm_profile", "cm_profile_read", "cm_last_error"]
+
+
+class CmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Model(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("kind", C.c_uint32), ("precision", C.c_uint32),
+                ("n_units", C.c_uint32), ("n_stimuli", C.c_uint32), ("n_signals", C.c_uint32),
+                ("params", C.POINTER(C.c_double)), ("n_params", C.c_uint32),
+                ("weights", C.c_void_p), ("n_weights", C.c_uint64)]
+
+
+class Sweep(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("n_settings", C.c_uint64), ("trials", C.c_uint64),
+                ("seed", C.c_uint64), ("max_steps", C.c_uint32), ("n_bins", C.c_uint32),
+                ("reward", C.c_double), ("cost", C.c_double), ("flag_eps", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("hist", C.c_void_p), ("stats", C.c_void_p), ("score", C.c_void_p),
+                ("best", C.c_void_p), ("run_choice", C.c_void_p), ("run_step", C.c_void_p),
+                ("run_flag", C.c_void_p), ("run_state", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("runs_per_lane", C.c_uint32),
+                ("steps_per_sync", C.c_uint32), ("tile_rows", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcm.so (PyTorch first, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  -- loads PyTorch's HIP runtime before libcm's dependency
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2110_15425_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.cm_validate.argtypes = [C.POINTER(Model), C.POINTER(Sweep)]
+        L.cm_workspace_bytes.argtypes = [C.POINTER(Model), C.POINTER(Sweep), C.POINTER(C.c_uint64)]
+        L.cm_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+        L.cm_destroy.argtypes = [C.c_void_p]
+        L.cm_set_tuning.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(Tuning)]
+        L.cm_get_tuning.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(Tuning)]
+        L.cm_launch.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.POINTER(Result),
+                                C.c_void_p, C.c_uint64, C.c_void_p]
+        L.cm_profile.argtypes = [C.c_void_p, C.c_int]
+        L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+        L.cm_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "cm_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise CmError(status, lib().cm_last_error().decode())
+
+
+def structs(w, weights_ptr=None, grid_ptr=None):
+    """cm_model / cm_sweep for a workload dict; device pointers passed in."""
+    params = np.ascontiguousarray(w["params"], np.float64)
+    nw = 0 if w.get("weights") is None else int(np.asarray(w["weights"]).size)
+    m = Model(ABI_VERSION, int(w["kind"]), int(w["precision"]), int(w["n_units"]),
+              int(w["n_stimuli"]), int(w["n_signals"]),
+              params.ctypes.data_as(C.POINTER(C.c_double)), params.size,
+              weights_ptr, nw)
+    s = Sweep(grid_ptr, int(w["n_settings"]), int(w["trials"]), int(w["seed"]),
+              int(w["max_steps"]), int(w["n_bins"]), float(w.get("reward", 0.0)),
+              float(w.get("cost", 0.0)), float(w.get("flag_eps", 1e-10)))
+    return m, s, params
+
+
+def validate(w):
+    """Host-only validation; returns the cm_status."""
+    m, s, keep = structs(w, weights_ptr=None if w.get("weights") is None else 8,
+                         grid_ptr=None if w["n_signals"] == 0 else 8)
+    return lib().cm_validate(C.byref(m), C.byref(s))
+
+
+def workspace_bytes(w):
+    m, s, keep = structs(w, weights_ptr=None if w.get("weights") is None else 8,
+                         grid_ptr=None if w["n_signals"] == 0 else 8)
+    n = C.c_uint64(0)
+    check(lib().cm_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)))
+    return int(n.value)
+
+
+def state_width(w):
+    return {0: 1, 1: 2}.get(int(w["kind"]), 2 + int(w["n_units"]))
+
+
+class Handle:
+    """A libcm handle on one device."""
+
+    def __init__(self, device=0):
+        h = C.c_void_p()
+        check(lib().cm_create(int(device), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().cm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable=True):
+        check(lib().cm_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed simulation-kernel milliseconds, number of timed launches)."""
+        ms, n = C.c_double(0), C.c_uint64(0)
+        check(lib().cm_profile_read(self.h, C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def set_tuning(self, kind, precision, block=0, runs_per_lane=0, steps_per_sync=0,
+                   tile_rows=0):
+        t = Tuning(block, runs_per_lane, steps_per_sync, tile_rows)
+        check(lib().cm_set_tuning(self.h, int(kind), int(precision), C.byref(t)))
+
+    def get_tuning(self, kind, precision):
+        t = Tuning()
+        check(lib().cm_get_tuning(self.h, int(kind), int(precision), C.byref(t)))
+        return dict(block=t.block, runs_per_lane=t.runs_per_lane,
+                    steps_per_sync=t.steps_per_sync, tile_rows=t.tile_rows)
+
+
+class DeviceSweep:
+    """Device-resident inputs, outputs and workspace of one sweep.
+
+    ``launch()`` enqueues the whole sweep on the current torch stream;
+    ``results()`` synchronises and copies the outputs to numpy."""
+
+    def __init__(self, handle, w, dumps=False):
+        import torch
+        self.torch = torch
+        self.handle = handle
+        self.w = w
+        dev = torch.device("cuda", handle.device)
+        S, T, B = int(w["n_settings"]), int(w["trials"]), int(w["n_bins"])
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.weights = None
+        if w.get("weights") is not None:
+            self.weights = torch.as_tensor(np.asarray(w["weights"], np.float64)).to(dev)
+        self.grid = None
+        if int(w["n_signals"]) > 0:
+            self.grid = torch.as_tensor(np.ascontiguousarray(w["grid"], np.float64)).to(dev)
+        self.hist = torch.empty((S, 2, B), dtype=torch.int64, device=dev)
+        self.stats = torch.empty((S, NSTAT), dtype=torch.int64, device=dev)
+        scored = float(w.get("reward", 0.0)) != 0.0 or float(w.get("cost", 0.0)) != 0.0
+        self.score = torch.empty(S, **f64) if scored else None
+        self.best = torch.empty(2, dtype=torch.int64, device=dev) if scored else None
+        self.dumps = dumps
+        if dumps:
+            runs = S * T
+            self.run_choice = torch.empty(runs, dtype=torch.int8, device=dev)
+            self.run_step = torch.empty(runs, dtype=torch.int32, device=dev)
+            self.run_flag = torch.empty(runs, dtype=torch.uint8, device=dev)
+            self.run_state = torch.empty((runs, state_width(w)), **f64)
+        self.model, self.sweep, self._params = structs(
+            w, None if self.weights is None else self.weights.data_ptr(),
+            None if self.grid is None else self.grid.data_ptr())
+        n = C.c_uint64(0)
+        check(lib().cm_workspace_bytes(C.byref(self.model), C.byref(self.sweep), C.byref(n)))
+        self.workspace = torch.empty(int(n.value), dtype=torch.uint8, device=dev)
+        ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        self.result = Result(ptr(self.hist), ptr(self.stats), ptr(self.score), ptr(self.best),
+                             ptr(self.run_choice) if dumps else None,
+                             ptr(self.run_step) if dumps else None,
+                             ptr(self.run_flag) if dumps else None,
+                             ptr(self.run_state) if dumps else None)
+
+    def launch(self, stream=None):
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
+        check(lib().cm_launch(self.handle.h, C.byref(self.model), C.byref(self.sweep),
+                              C.byref(self.result), C.c_void_p(self.workspace.data_ptr()),
+                              self.workspace.numel(), C.c_void_p(st.cuda_stream)))
+
+    def results(self):
+        self.torch.cuda.synchronize(self.handle.device)
+        out = dict(hist=self.hist.cpu().numpy().view(np.uint64),
+                   stats=self.stats.cpu().numpy().view(np.uint64),
+                   score=None if self.score is None else self.score.cpu().numpy(),
+                   best=None if self.best is None else self.best.cpu().numpy())
+        if self.dumps:
+            out["run_choice"] = self.run_choice.cpu().numpy()
+            out["run_step"] = self.run_step.cpu().numpy().view(np.uint32)
+            out["run_flag"] = self.run_flag.cpu().numpy()
+            out["run_state"] = self.run_state.cpu().numpy()
+        return out
+
+
+_default_handle = None
+
+
+def default_handle():
+    global _default_handle
+    if _default_handle is None:
+        _default_handle = Handle(0)
+    return _default_handle
+
+
+def run(w, dumps=False, handle=None):
+    """Run one sweep on the GPU and return its outputs as numpy arrays
+    (same keys as the oracle's)."""
+    ds = DeviceSweep(handle or default_handle(), w, dumps=dumps)
+    ds.launch()
+    return ds.results()
+
+
+def run_steps(w, out):
+    """Executed run-steps of a sweep, from its integer statistics."""
+    st = out["stats"].astype(np.uint64)
+    return int(st[:, ST["sumn0"]].sum() + st[:, ST["sumn1"]].sum()
+               + st[:, ST["undec"]].sum() * np.uint64(w["max_steps"]))

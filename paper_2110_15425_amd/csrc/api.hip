@@ -1,0 +1,399 @@
+// api.hip -- the C ABI of libcm: validation, workspace sizing, launch planning.
+//
+// Read-only model parameters are copied from the caller's host array into
+// kernel arguments at launch time; per-run read-write state never exists
+// outside the kernels' registers (the read-only/read-write split and
+// flat-array inputs/outputs of the Distill paper, Sec. 3.3).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.hpp"
+
+struct cm_handle {
+  int device;
+  int cu_count;
+  size_t lds_per_block;
+  cm_tuning tune[3][3];  // [kind][precision]
+  // kernel timing: event pairs recorded around simulation kernels
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cm_status fail(cm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+cm_status fail(cm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+cm_status ok() {
+  g_err.clear();
+  return CM_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+constexpr uint64_t kMaxChunk = 1u << 20;
+constexpr size_t kWorkspaceAlign = 256;
+constexpr size_t kLdsBudget = 32 * 1024;  // histogram window per workgroup
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+// Workspace layout (offsets in bytes from the workspace base).
+struct Layout {
+  uint64_t drive, correct, total;
+};
+
+Layout layout(const cm_model* m, const cm_sweep* s) {
+  Layout L{};
+  uint64_t off = 0;
+  L.correct = off;
+  off = align_up(off + 16 * sizeof(int32_t), kWorkspaceAlign);
+  L.drive = off;
+  if (m->kind == CM_CONFLICT_LCA) off = align_up(off + s->n_settings * 9u * 2u * sizeof(double), kWorkspaceAlign);
+  L.total = std::max<uint64_t>(off, kWorkspaceAlign);
+  return L;
+}
+
+cm_status check_model_sweep(const cm_model* m, const cm_sweep* s) {
+  if (!m || !s) return fail(CM_E_INVALID, "model and sweep must not be NULL");
+  if (m->abi_version != CM_ABI_VERSION)
+    return fail(CM_E_INVALID, "abi_version %u, library speaks %u", m->abi_version, CM_ABI_VERSION);
+  if (!m->params) return fail(CM_E_INVALID, "params must not be NULL");
+  if (s->n_settings < 1 || s->n_settings >= 0xFFFFFFFFull)
+    return fail(CM_E_INVALID, "n_settings must be in [1, 2^32-2]");
+  if (s->trials < 1 || s->trials >= (1ull << 31)) return fail(CM_E_INVALID, "trials must be in [1, 2^31)");
+  if (s->n_settings > (1ull << 62) / s->trials) return fail(CM_E_INVALID, "too many runs");
+  if (s->max_steps < 1) return fail(CM_E_INVALID, "max_steps must be >= 1");
+  if (s->n_bins < 1 || s->n_bins > s->max_steps) return fail(CM_E_INVALID, "n_bins must be in [1, max_steps]");
+  if ((uint64_t)s->n_bins * s->max_steps >= (1ull << 32))
+    return fail(CM_E_INVALID, "n_bins * max_steps must be < 2^32");
+  if (!(s->flag_eps >= 0.0) || !isfinite(s->flag_eps)) return fail(CM_E_INVALID, "flag_eps must be finite and >= 0");
+  if (!isfinite(s->reward) || !isfinite(s->cost)) return fail(CM_E_INVALID, "reward and cost must be finite");
+  if (m->n_signals > 0 && !s->grid) return fail(CM_E_INVALID, "grid must not be NULL when n_signals > 0");
+  if (s->grid && !aligned(s->grid, 8)) return fail(CM_E_INVALID, "grid must be 8-byte aligned");
+  const double* p = m->params;
+  switch (m->kind) {
+    case CM_DDM:
+      if (m->n_params < CM_DDM_NPARAM) return fail(CM_E_INVALID, "DDM needs %d params", CM_DDM_NPARAM);
+      if (m->n_units != 1 || m->n_stimuli != 1 || m->n_signals > 1)
+        return fail(CM_E_INVALID, "DDM: n_units 1, n_stimuli 1, n_signals 0 or 1");
+      if (!(p[CM_DDM_DT] > 0) || !isfinite(p[CM_DDM_DT])) return fail(CM_E_INVALID, "dt must be > 0");
+      if (!(p[CM_DDM_NOISE] >= 0) || !isfinite(p[CM_DDM_NOISE])) return fail(CM_E_INVALID, "noise must be >= 0");
+      if (!(p[CM_DDM_THRESH] > 0)) return fail(CM_E_INVALID, "threshold must be > 0");
+      if (!(fabs(p[CM_DDM_START]) < p[CM_DDM_THRESH])) return fail(CM_E_INVALID, "|start| must be < threshold");
+      if (!isfinite(p[CM_DDM_DRIFT])) return fail(CM_E_INVALID, "drift must be finite");
+      if (m->precision == CM_BF16_PROJ) return fail(CM_E_UNSUPPORTED, "bf16 projection applies to the rate network only");
+      break;
+    case CM_CONFLICT_LCA:
+      if (m->n_params < CM_LCA_NPARAM) return fail(CM_E_INVALID, "LCA needs %d params", CM_LCA_NPARAM);
+      if (m->n_units != 2 || m->n_stimuli != 9 || (m->n_signals != 0 && m->n_signals != 2))
+        return fail(CM_E_INVALID, "conflict LCA: n_units 2, n_stimuli 9, n_signals 0 or 2");
+      if (!m->weights || m->n_weights < 40) return fail(CM_E_INVALID, "conflict LCA needs 40 weights");
+      if (!aligned(m->weights, 8)) return fail(CM_E_INVALID, "weights must be 8-byte aligned");
+      if (!(p[CM_LCA_DT] > 0) || !isfinite(p[CM_LCA_DT])) return fail(CM_E_INVALID, "dt must be > 0");
+      if (!(p[CM_LCA_NOISE] >= 0) || !isfinite(p[CM_LCA_NOISE])) return fail(CM_E_INVALID, "noise must be >= 0");
+      if (!(p[CM_LCA_THRESH] > 0)) return fail(CM_E_INVALID, "threshold must be > 0");
+      for (int i : {CM_LCA_LEAK, CM_LCA_COMP, CM_LCA_OFFSET, CM_LCA_HID_GAIN, CM_LCA_HID_BIAS})
+        if (!isfinite(p[i])) return fail(CM_E_INVALID, "LCA parameter %d must be finite", i);
+      if (m->precision == CM_BF16_PROJ) return fail(CM_E_UNSUPPORTED, "bf16 projection applies to the rate network only");
+      break;
+    case CM_RATE_RNN:
+      if (m->n_params < CM_RNN_NPARAM) return fail(CM_E_INVALID, "rate network needs %d params", CM_RNN_NPARAM);
+      if (m->n_units < 64 || m->n_units > 256 || m->n_units % 64 || m->n_stimuli != 1 || m->n_signals > 1)
+        return fail(CM_E_INVALID, "rate network: n_units in {64,128,192,256}, n_stimuli 1, n_signals 0 or 1");
+      if (!m->weights || m->n_weights < (uint64_t)m->n_units * m->n_units + 2u * m->n_units)
+        return fail(CM_E_INVALID, "rate network needs n*n + 2n weights");
+      if (!aligned(m->weights, 8)) return fail(CM_E_INVALID, "weights must be 8-byte aligned");
+      if (!(p[CM_RNN_DT] > 0) || !isfinite(p[CM_RNN_DT])) return fail(CM_E_INVALID, "dt must be > 0");
+      if (!(p[CM_RNN_NOISE] >= 0) || !isfinite(p[CM_RNN_NOISE])) return fail(CM_E_INVALID, "noise must be >= 0");
+      if (!(p[CM_RNN_THRESH] > 0)) return fail(CM_E_INVALID, "threshold must be > 0");
+      return fail(CM_E_UNSUPPORTED, "rate network kernels are not built in this library");
+    default:
+      return fail(CM_E_INVALID, "unknown kind %u", m->kind);
+  }
+  if (m->precision > CM_BF16_PROJ) return fail(CM_E_INVALID, "unknown precision %u", m->precision);
+  return ok();
+}
+
+cm_status check_result(const cm_model* m, const cm_sweep* s, const cm_result* r) {
+  if (!r || !r->hist || !r->stats) return fail(CM_E_INVALID, "hist and stats must not be NULL");
+  if (!aligned(r->hist, 8) || !aligned(r->stats, 8)) return fail(CM_E_INVALID, "hist/stats must be 8-byte aligned");
+  const bool scored = s->reward != 0.0 || s->cost != 0.0;
+  if (scored && !r->score) return fail(CM_E_INVALID, "score must not be NULL when reward or cost is set");
+  if (r->score && !aligned(r->score, 8)) return fail(CM_E_INVALID, "score must be 8-byte aligned");
+  if (r->best && !scored) return fail(CM_E_INVALID, "best requires reward or cost");
+  if (r->best && !aligned(r->best, 8)) return fail(CM_E_INVALID, "best must be 8-byte aligned");
+  const bool any_dump = r->run_choice || r->run_step || r->run_flag || r->run_state;
+  if (any_dump && !(r->run_choice && r->run_step && r->run_flag))
+    return fail(CM_E_INVALID, "run_choice, run_step and run_flag are dumped together");
+  if (r->run_step && !aligned(r->run_step, 4)) return fail(CM_E_INVALID, "run_step must be 4-byte aligned");
+  if (r->run_state && !aligned(r->run_state, 8)) return fail(CM_E_INVALID, "run_state must be 8-byte aligned");
+  (void)m;
+  return ok();
+}
+
+cm_tuning default_tuning(uint32_t kind, uint32_t prec) {
+  cm_tuning t{};
+  t.block = 256;
+  t.runs_per_lane = 2;
+  t.steps_per_sync = kind == CM_DDM ? 4 : 8;  // DDM counts step pairs
+  t.tile_rows = 64;
+  (void)prec;
+  return t;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+cm_status hip_fail(hipError_t e, const char* what) {
+  return fail(CM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cm_last_error(void) { return g_err.c_str(); }
+
+cm_status cm_validate(const cm_model* model, const cm_sweep* sweep) {
+  return check_model_sweep(model, sweep);
+}
+
+cm_status cm_workspace_bytes(const cm_model* model, const cm_sweep* sweep, uint64_t* bytes) {
+  if (!bytes) return fail(CM_E_INVALID, "bytes must not be NULL");
+  cm_status st = check_model_sweep(model, sweep);
+  if (st != CM_OK) return st;
+  *bytes = layout(model, sweep).total;
+  return ok();
+}
+
+cm_status cm_create(int device_ordinal, cm_handle** out) {
+  if (!out) return fail(CM_E_INVALID, "out must not be NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device_ordinal < 0 || device_ordinal >= n)
+    return fail(CM_E_INVALID, "device %d out of range (%d devices)", device_ordinal, n);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device_ordinal);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  cm_handle* h = new (std::nothrow) cm_handle();
+  if (!h) return fail(CM_E_DEVICE, "out of host memory");
+  h->device = device_ordinal;
+  h->cu_count = prop.multiProcessorCount;
+  h->lds_per_block = prop.sharedMemPerBlock;
+  for (uint32_t k = 0; k < 3; ++k)
+    for (uint32_t p = 0; p < 3; ++p) h->tune[k][p] = default_tuning(k, p);
+  *out = h;
+  return ok();
+}
+
+cm_status cm_destroy(cm_handle* h) {
+  if (h) {
+    for (auto& ev : h->events) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  }
+  delete h;
+  return ok();
+}
+
+cm_status cm_profile(cm_handle* h, int enable) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  h->prof = enable != 0;
+  h->used = 0;
+  return ok();
+}
+
+cm_status cm_profile_read(cm_handle* h, double* sim_ms, uint64_t* launches) {
+  if (!h || !sim_ms || !launches) return fail(CM_E_INVALID, "NULL argument");
+  double total = 0.0;
+  for (size_t i = 0; i < h->used; ++i) {
+    hipError_t e = hipEventSynchronize(h->events[i].second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, h->events[i].first, h->events[i].second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    total += ms;
+  }
+  *sim_ms = total;
+  *launches = h->used;
+  return ok();
+}
+
+cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const cm_tuning* t) {
+  if (!h || !t || kind > 2 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
+  cm_tuning v = *t;
+  const cm_tuning d = default_tuning(kind, precision);
+  if (!v.block) v.block = d.block;
+  if (!v.runs_per_lane) v.runs_per_lane = d.runs_per_lane;
+  if (!v.steps_per_sync) v.steps_per_sync = d.steps_per_sync;
+  if (!v.tile_rows) v.tile_rows = d.tile_rows;
+  if (v.block != 256) return fail(CM_E_UNSUPPORTED, "block must be 256");
+  if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
+  if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");
+  if (v.tile_rows != 16 && v.tile_rows != 32 && v.tile_rows != 64)
+    return fail(CM_E_INVALID, "tile_rows must be 16, 32 or 64");
+  h->tune[kind][precision] = v;
+  return ok();
+}
+
+cm_status cm_get_tuning(cm_handle* h, uint32_t kind, uint32_t precision, cm_tuning* t) {
+  if (!h || !t || kind > 2 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
+  *t = h->tune[kind][precision];
+  return ok();
+}
+
+cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                    void* workspace, uint64_t workspace_bytes, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  st = check_result(m, s, r);
+  if (st != CM_OK) return st;
+  const Layout L = layout(m, s);
+  if (!workspace || !aligned(workspace, kWorkspaceAlign))
+    return fail(CM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(CM_E_BUDGET, "workspace has %llu bytes, needs %llu",
+                (unsigned long long)workspace_bytes, (unsigned long long)L.total);
+  const cm_tuning& tune = h->tune[m->kind][m->precision];
+  hipStream_t stream = (hipStream_t)hip_stream;
+  char* ws = (char*)workspace;
+  const double* p = m->params;
+  const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
+  const uint32_t B = s->n_bins;
+
+  // launch plan for the lane-per-run kernels
+  cm::SimArgs a{};
+  a.trials = T;
+  a.n_settings = S;
+  a.total_runs = runs;
+  a.seed = s->seed;
+  a.max_steps = s->max_steps;
+  a.n_bins = B;
+  a.n_signals = m->n_signals;
+  a.flag_eps = s->flag_eps;
+  a.grid = s->grid;
+  a.hist = r->hist;
+  a.stats = r->stats;
+  a.run_choice = r->run_choice;
+  a.run_step = r->run_step;
+  a.run_flag = r->run_flag;
+  a.run_state = r->run_state;
+  a.steps_per_sync = tune.steps_per_sync;
+  a.correct = (const int32_t*)(ws + L.correct);
+  if (m->kind == CM_DDM) {
+    a.dt = p[CM_DDM_DT];
+    a.drift = p[CM_DDM_DRIFT];
+    a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
+    a.thresh = p[CM_DDM_THRESH];
+    a.start = p[CM_DDM_START];
+  } else {
+    a.dt = p[CM_LCA_DT];
+    a.leak = p[CM_LCA_LEAK];
+    a.comp = p[CM_LCA_COMP];
+    a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
+    a.thresh = p[CM_LCA_THRESH];
+    a.nonneg = p[CM_LCA_NONNEG] != 0.0;
+    a.drive = (const double*)(ws + L.drive);
+  }
+  uint64_t chunk = (uint64_t)tune.block * tune.runs_per_lane;
+  chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, tune.block), kMaxChunk);
+  const size_t rec_bytes = 4u * cm::rec_words(B);
+  const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
+  bool direct = false;
+  // settings touched by one chunk: at most floor((chunk-1)/T) + 2
+  if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
+    const uint64_t fit = wmax >= 2 ? (wmax - 1) * T : 0;
+    if (fit >= tune.block) chunk = fit;
+    else direct = true;
+  }
+  a.chunk = chunk;
+  a.window = direct ? 0 : (uint32_t)std::min<uint64_t>((chunk - 1) / T + 2, S);
+  const uint64_t groups = (runs + chunk - 1) / chunk;
+  if (groups > 0x7FFFFFFFull) return fail(CM_E_INVALID, "sweep too large for one launch");
+  const size_t lds = direct ? 0 : (size_t)a.window * rec_bytes;
+
+  DeviceGuard guard(h->device);
+  hipError_t e;
+  if ((e = cm::launch_zero_u64(r->hist, S * 2u * B, stream)) != hipSuccess) return hip_fail(e, "zero hist");
+  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
+  if (m->kind == CM_DDM) {
+    // correct response per stimulus: the upper boundary
+    if ((e = cm::launch_fill_i32((int32_t*)(ws + L.correct), 1, 1, stream)) != hipSuccess)
+      return hip_fail(e, "correct table");
+  } else {
+    cm::DriveArgs d{};
+    d.n_settings = S;
+    d.n_signals = m->n_signals;
+    d.gain = p[CM_LCA_HID_GAIN];
+    d.bias = p[CM_LCA_HID_BIAS];
+    d.offset = p[CM_LCA_OFFSET];
+    d.weights = m->weights;
+    d.grid = s->grid;
+    d.drive = (double*)(ws + L.drive);
+    d.correct = (int32_t*)(ws + L.correct);
+    if ((e = cm::launch_drive(d, stream)) != hipSuccess) return hip_fail(e, "drive precompute");
+  }
+  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+  if (h->prof) {
+    if (h->used == h->events.size()) {
+      std::pair<hipEvent_t, hipEvent_t> p{};
+      if ((e = hipEventCreate(&p.first)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+      if ((e = hipEventCreate(&p.second)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+      h->events.push_back(p);
+    }
+    ev = &h->events[h->used++];
+    if ((e = hipEventRecord(ev->first, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
+  if ((e = cm::launch_sim_lane(m->kind, m->precision, direct, a, tune.block, groups, lds, stream)) != hipSuccess)
+    return hip_fail(e, "simulation kernel");
+  if (ev && (e = hipEventRecord(ev->second, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if (s->reward != 0.0 || s->cost != 0.0) {
+    cm::ScoreArgs sa{};
+    sa.n_settings = S;
+    sa.trials = T;
+    sa.seed = s->seed;
+    sa.n_signals = m->n_signals;
+    sa.reward = s->reward;
+    sa.cost = s->cost;
+    sa.grid = s->grid;
+    sa.stats = r->stats;
+    sa.score = r->score;
+    sa.best = r->best;
+    if ((e = cm::launch_score(sa, stream)) != hipSuccess) return hip_fail(e, "score kernel");
+  }
+  return ok();
+}
+
+}  // extern "C"

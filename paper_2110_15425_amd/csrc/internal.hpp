@@ -1,0 +1,65 @@
+// internal.hpp -- host/device declarations shared by libcm's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cm.h"
+
+namespace cm {
+
+// Per-setting record of the LDS histogram window, in 32-bit words:
+// hist[2][B] counts, 8 count words (dec0, dec1, undec, correct, flagged, pad),
+// then 4 uint64 sums (sum n for choice 0/1, sum n^2 for choice 0/1).
+enum { kCntDec0 = 0, kCntDec1, kCntUndec, kCntCorrect, kCntFlagged, kCntWords = 8 };
+__host__ __device__ inline uint32_t rec_words(uint32_t n_bins) { return 2u * n_bins + kCntWords + 8u; }
+
+// Arguments of the lane-per-run simulation kernels (DDM, conflict LCA).
+struct SimArgs {
+  uint64_t trials, n_settings, total_runs, seed;
+  uint64_t chunk;     // runs handed to one workgroup
+  uint32_t max_steps, n_bins, n_signals, window, steps_per_sync;
+  double thresh, flag_eps, b, dt;
+  double drift, start;  // DDM
+  double leak, comp;    // LCA
+  uint32_t nonneg;
+  const double* grid;
+  const double* drive;     // LCA: [settings][9][2]
+  const int32_t* correct;  // [stimuli]
+  uint64_t* hist;
+  uint64_t* stats;
+  int8_t* run_choice;
+  uint32_t* run_step;
+  uint8_t* run_flag;
+  double* run_state;
+};
+
+struct ScoreArgs {
+  uint64_t n_settings, trials, seed;
+  uint32_t n_signals;
+  double reward, cost;
+  const double* grid;
+  const uint64_t* stats;
+  double* score;
+  int64_t* best;
+};
+
+struct DriveArgs {
+  uint64_t n_settings;
+  uint32_t n_signals;
+  double gain, bias, offset;
+  const double* weights;
+  const double* grid;
+  double* drive;     // [settings][9][2]
+  int32_t* correct;  // [9]
+};
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_sim_lane(int kind, int precision, bool direct, const SimArgs& a, uint32_t block,
+                           uint64_t n_groups, size_t lds_bytes, hipStream_t st);
+hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st);
+hipError_t launch_drive(const DriveArgs& a, hipStream_t st);
+hipError_t launch_score(const ScoreArgs& a, hipStream_t st);
+
+}  // namespace cm

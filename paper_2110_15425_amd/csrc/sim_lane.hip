@@ -1,0 +1,306 @@
+// sim_lane.hip -- one wavefront lane per run: the drift-diffusion model and the
+// conflict network's leaky competing accumulator.
+//
+// Each run is an evaluation of the model's trial loop (Distill, Sec. 2.2):
+// the mechanisms are stepped until a threshold is crossed or the step cap is
+// reached.  Runs are independent (Sec. 3.6), so every lane owns one run with
+// its whole state in registers; read-only parameters arrive as kernel
+// arguments (the RO/RW split of Sec. 3.3) and the loop-invariant
+// feed-forward drive of the conflict network is precomputed once per
+// (setting, stimulus) by a separate kernel (the cross-node loop-invariant
+// code motion of Sec. 3.5).
+//
+// Scheduling: a workgroup owns a contiguous chunk of runs (setting-major).
+// Lanes claim runs from an LDS counter; a lane whose run ended takes the next
+// one at the following refill point, so waves stay dense while run lengths
+// vary by orders of magnitude.  Finished runs are counted into an LDS
+// histogram covering the few settings the chunk spans and flushed with one
+// global 64-bit atomic per nonzero bin when the chunk is done.  All
+// reductions are integer additions: results do not depend on the schedule.
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace cm {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Lane {
+  uint32_t s, t;   // setting, trial
+  uint32_t n;      // executed steps
+  int32_t target;  // correct response for this trial's stimulus (-1: none)
+  int choice;      // -1 undecided
+  bool flag;
+};
+
+__device__ __forceinline__ bool near_th(double q, double th, double eps) {
+  return fabs(q - th) < eps;
+}
+
+// Record one finished run: LDS window (or global atomics in direct mode) and
+// optional per-run dumps.
+template <bool DIRECT>
+__device__ __forceinline__ void record(const SimArgs& a, uint32_t* lds, uint32_t s_lo,
+                                       const Lane& L, const double* state, int width) {
+  const uint64_t n = L.n;
+  const int c = L.choice;
+  if (DIRECT) {
+    uint64_t* st = a.stats + (uint64_t)L.s * CM_NSTAT;
+    if (c >= 0) {
+      const uint32_t bin = ((L.n - 1u) * a.n_bins) / a.max_steps;
+      atomicAdd((unsigned long long*)&a.hist[((uint64_t)L.s * 2u + c) * a.n_bins + bin], 1ull);
+      atomicAdd((unsigned long long*)&st[CM_ST_DEC0 + c], 1ull);
+      atomicAdd((unsigned long long*)&st[CM_ST_SUMN0 + c], (unsigned long long)n);
+      atomicAdd((unsigned long long*)&st[CM_ST_SUMSQ0 + c], (unsigned long long)(n * n));
+      if (c == L.target) atomicAdd((unsigned long long*)&st[CM_ST_CORRECT], 1ull);
+    } else {
+      atomicAdd((unsigned long long*)&st[CM_ST_UNDEC], 1ull);
+    }
+    if (L.flag) atomicAdd((unsigned long long*)&st[CM_ST_FLAGGED], 1ull);
+  } else {
+    const uint32_t B = a.n_bins;
+    uint32_t* rec = lds + (L.s - s_lo) * rec_words(B);
+    uint32_t* cnt = rec + 2u * B;
+    unsigned long long* sums = (unsigned long long*)(cnt + kCntWords);
+    if (c >= 0) {
+      const uint32_t bin = ((L.n - 1u) * B) / a.max_steps;
+      atomicAdd(&rec[c * B + bin], 1u);
+      atomicAdd(&cnt[kCntDec0 + c], 1u);
+      if (c == L.target) atomicAdd(&cnt[kCntCorrect], 1u);
+      atomicAdd(&sums[c], (unsigned long long)n);
+      atomicAdd(&sums[2 + c], (unsigned long long)(n * n));
+    } else {
+      atomicAdd(&cnt[kCntUndec], 1u);
+    }
+    if (L.flag) atomicAdd(&cnt[kCntFlagged], 1u);
+  }
+  if (a.run_choice) {
+    const uint64_t idx = (uint64_t)L.s * a.trials + L.t;
+    a.run_choice[idx] = (int8_t)c;
+    a.run_step[idx] = L.n;
+    a.run_flag[idx] = L.flag ? 1 : 0;
+    if (a.run_state)
+      for (int i = 0; i < width; ++i) a.run_state[idx * width + i] = state[i];
+  }
+}
+
+// Flush the LDS window into the global histogram and statistics.
+__device__ void flush(const SimArgs& a, const uint32_t* lds, uint32_t s_lo) {
+  const uint32_t B = a.n_bins, per = 2u * B + CM_NSTAT, rw = rec_words(B);
+  for (uint32_t i = threadIdx.x; i < a.window * per; i += blockDim.x) {
+    const uint32_t w = i / per, j = i - w * per;
+    const uint64_t sg = (uint64_t)s_lo + w;
+    if (sg >= a.n_settings) continue;
+    const uint32_t* rec = lds + w * rw;
+    const uint32_t* cnt = rec + 2u * B;
+    const unsigned long long* sums = (const unsigned long long*)(cnt + kCntWords);
+    unsigned long long v;
+    unsigned long long* dst;
+    if (j < 2u * B) {
+      v = rec[j];
+      dst = (unsigned long long*)&a.hist[sg * 2u * B + j];
+    } else {
+      const uint32_t k = j - 2u * B;
+      switch (k) {
+        case CM_ST_DEC0: v = cnt[kCntDec0]; break;
+        case CM_ST_DEC1: v = cnt[kCntDec1]; break;
+        case CM_ST_UNDEC: v = cnt[kCntUndec]; break;
+        case CM_ST_CORRECT: v = cnt[kCntCorrect]; break;
+        case CM_ST_SUMN0: v = sums[0]; break;
+        case CM_ST_SUMN1: v = sums[1]; break;
+        case CM_ST_SUMSQ0: v = sums[2]; break;
+        case CM_ST_SUMSQ1: v = sums[3]; break;
+        default: v = cnt[kCntFlagged]; break;
+      }
+      dst = (unsigned long long*)&a.stats[sg * CM_NSTAT + k];
+    }
+    if (v) atomicAdd(dst, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mechanisms.  Each model provides: begin(lane) -- set up a run; advance() --
+// execute up to `steps` steps (a step pair per random block for the DDM),
+// returning false once the run has ended; state() for dumps.
+// ---------------------------------------------------------------------------
+
+// Drift-diffusion (Euler-Maruyama): x <- (x + a) + b z, bounds +-theta.
+// Step n uses element (n-1) & 1 of block (n-1) >> 1.
+template <int PREC>
+struct DDM {
+  double x, a_step;
+  static constexpr int kWidth = 1;
+
+  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L) {
+    const double drift = A.n_signals ? A.grid[(uint64_t)L.s * A.n_signals] : A.drift;
+    a_step = drift * A.dt;
+    x = A.start;
+    L.target = 1;  // the upper boundary is the correct response
+  }
+
+  __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, double z, float zf, float af,
+                                      float bf) {
+    if (PREC == CM_FP64) x = (x + a_step) + A.b * z;
+    else x = x + (double)fmaf(bf, zf, af);
+    L.n += 1;
+    const double th = A.thresh;
+    if (near_th(x, th, A.flag_eps) || near_th(x, -th, A.flag_eps)) L.flag = true;
+    if (x >= th) { L.choice = 1; return false; }
+    if (x <= -th) { L.choice = 0; return false; }
+    if (L.n == A.max_steps) { L.choice = -1; return false; }
+    return true;
+  }
+
+  __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                          int pairs) {
+    const float af = (float)a_step, bf = (float)A.b;
+    for (int p = 0; p < pairs; ++p) {
+      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
+      double z0 = 0, z1 = 0;
+      float f0 = 0, f1 = 0;
+      if (PREC == CM_FP64) normals64(w, z0, z1);
+      else normals32(w, f0, f1);
+      if (!one(A, L, z0, f0, af, bf)) return false;
+      if (!one(A, L, z1, f1, af, bf)) return false;
+    }
+    return true;
+  }
+
+  __device__ __forceinline__ void state(double* out) const { out[0] = x; }
+};
+
+// Two-unit leaky competing accumulator with simultaneous update:
+// x_i <- x_i + ((I_i - leak x_i - comp x_j) dt) + b z_i.
+template <int PREC>
+struct LCA {
+  double x0, x1, in0, in1;
+  static constexpr int kWidth = 2;
+
+  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L) {
+    const uint32_t stim = L.t % 9u;
+    const double* d = A.drive + ((uint64_t)L.s * 9u + stim) * 2u;
+    in0 = d[0];
+    in1 = d[1];
+    x0 = 0.0;
+    x1 = 0.0;
+    L.target = A.correct[stim];
+  }
+
+  __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                          int steps) {
+    const double th = A.thresh, eps = A.flag_eps;
+    for (int k = 0; k < steps; ++k) {
+      const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
+      double y0, y1;
+      if (PREC == CM_FP64) {
+        double z0, z1;
+        normals64(w, z0, z1);
+        y0 = (x0 + (((in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
+        y1 = (x1 + (((in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
+      } else {
+        float z0, z1;
+        normals32(w, z0, z1);
+        const float xf0 = (float)x0, xf1 = (float)x1;
+        const float lf = (float)A.leak, cf = (float)A.comp, df = (float)A.dt, bf = (float)A.b;
+        const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
+        const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
+        y0 = x0 + (double)fmaf(bf, z0, i0 * df);
+        y1 = x1 + (double)fmaf(bf, z1, i1 * df);
+      }
+      if (A.nonneg) {
+        if (y0 < 0.0) y0 = 0.0;
+        if (y1 < 0.0) y1 = 0.0;
+      }
+      x0 = y0;
+      x1 = y1;
+      L.n += 1;
+      if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+      const double mx = x0 > x1 ? x0 : x1;
+      if (mx >= th) {
+        L.choice = (x1 > x0) ? 1 : 0;
+        if (fabs(x0 - x1) < eps) L.flag = true;
+        return false;
+      }
+      if (L.n == A.max_steps) { L.choice = -1; return false; }
+    }
+    return true;
+  }
+
+  __device__ __forceinline__ void state(double* out) const {
+    out[0] = x0;
+    out[1] = x1;
+  }
+};
+
+template <class M, bool DIRECT>
+__global__ __launch_bounds__(kBlock) void sim_lane_kernel(SimArgs a) {
+  extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
+  uint32_t* lds = (uint32_t*)lds_u64;
+  __shared__ uint32_t next;
+  const uint64_t r0 = (uint64_t)blockIdx.x * a.chunk;
+  const uint64_t r1 = min(r0 + a.chunk, a.total_runs);
+  const uint32_t len = (uint32_t)(r1 - r0);
+  const uint32_t s_lo = (uint32_t)(r0 / a.trials);
+  const uint32_t t_lo = (uint32_t)(r0 - (uint64_t)s_lo * a.trials);
+  const uint32_t T = (uint32_t)a.trials;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+
+  if (!DIRECT)
+    for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
+  if (threadIdx.x == 0) next = blockDim.x;
+  __syncthreads();
+
+  M m;
+  Lane L;
+  uint32_t off = threadIdx.x;
+  bool have = off < len;
+  auto setup = [&](uint32_t o) {
+    const uint32_t local = t_lo + o;  // < 2^31 + chunk
+    L.s = s_lo + local / T;
+    L.t = local - (L.s - s_lo) * T;
+    L.n = 0;
+    L.choice = -1;
+    L.flag = false;
+    m.begin(a, L);
+  };
+  if (have) setup(off);
+
+  while (__any(have)) {
+    bool running = have;
+    if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync);
+    if (have && !running) {
+      double st[M::kWidth];
+      m.state(st);
+      record<DIRECT>(a, lds, s_lo, L, st, M::kWidth);
+      off = atomicAdd(&next, 1u);
+      have = off < len;
+      if (have) setup(off);
+    }
+  }
+  if (!DIRECT) {
+    __syncthreads();
+    flush(a, lds, s_lo);
+  }
+}
+
+template <class M>
+hipError_t launch_model(bool direct, const SimArgs& a, uint64_t n_groups, size_t lds,
+                        hipStream_t st) {
+  if (direct) hipLaunchKernelGGL((sim_lane_kernel<M, true>), dim3(n_groups), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL((sim_lane_kernel<M, false>), dim3(n_groups), dim3(kBlock), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sim_lane(int kind, int precision, bool direct, const SimArgs& a, uint32_t block,
+                           uint64_t n_groups, size_t lds_bytes, hipStream_t st) {
+  if (block != kBlock) return hipErrorInvalidValue;
+  if (kind == CM_DDM)
+    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(direct, a, n_groups, lds_bytes, st)
+                                : launch_model<DDM<CM_FP32_STEP>>(direct, a, n_groups, lds_bytes, st);
+  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(direct, a, n_groups, lds_bytes, st)
+                              : launch_model<LCA<CM_FP32_STEP>>(direct, a, n_groups, lds_bytes, st);
+}
+
+}  // namespace cm

@@ -1,0 +1,126 @@
+"""GPU parity: libcm through its C ABI against the FP64 CPU oracle on the
+same seeded inputs.  FP64 mode: per-run choice and decision step bit-exact
+on unflagged runs, final states within 1e-9 relative, histograms and
+statistics identical; scores bit-identical and the same best setting."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_15425_amd import cm, workloads as W
+from parity import assert_parity, hist_l1
+
+pytestmark = pytest.mark.gpu
+
+
+def _correct(w):
+    if w["kind"] == W.DDM:
+        return [1]
+    if w["kind"] == W.LCA:
+        return oracle.conflict_correct(w["weights"], w["params"][W.LCA_P["hid_gain"]],
+                                       w["params"][W.LCA_P["hid_bias"]])
+    return [-1]
+
+
+def _both(w, **kw):
+    print(f"case kind={w['kind']} prec={w['precision']} S={w['n_settings']} T={w['trials']} "
+          f"N={w['max_steps']} B={w['n_bins']} seed={w['seed']}", flush=True)
+    g = cm.run(w, dumps=True, **kw)
+    o = oracle.run(w, dumps=True)
+    return g, o
+
+
+DDM_CASES = {
+    "reference": W.ddm(),
+    "ragged": W.ddm(trials=1037, seed=5),
+    "drift_grid": W.ddm(trials=700, seed=3, drifts=np.linspace(0, 0.6, 37)),
+    "one_trial_many_settings": W.ddm(trials=1, seed=9, drifts=np.linspace(-0.5, 0.5, 3001)),
+    "cap_one_step": W.ddm(trials=300, max_steps=1, n_bins=1),
+    "odd_cap": W.ddm(trials=2000, max_steps=77, n_bins=7, noise=0.3),
+    "bins_equal_steps": W.ddm(trials=2000, max_steps=500, n_bins=500),
+    "noise_free": W.ddm(trials=100, noise=0.0),
+    "start_near_bound": W.ddm(trials=3000, start=0.999, dt=0.001),
+    "high_seed": W.ddm(trials=2000, seed=(123 << 40) | 77),
+}
+
+
+@pytest.mark.parametrize("name", list(DDM_CASES))
+def test_ddm_fp64_parity(name):
+    w = DDM_CASES[name]
+    g, o = _both(w)
+    assert_parity(w, g, o, _correct(w))
+
+
+LCA_CASES = {
+    "reference_c1": W.conflict(),
+    "grid_c2": W.grid_search(),
+    "ragged": W.conflict(trials=1001, seed=4, grid=W.control_grid(5)),
+    "one_trial": W.conflict(trials=1, seed=2, grid=W.control_grid(40)),
+    "no_signals": W.with_(W.conflict(trials=5000, seed=6), grid=None),
+    "nonneg": W.conflict(trials=3000, seed=7, nonneg=1.0, max_steps=300, n_bins=30),
+    "short_cap": W.conflict(trials=4000, seed=8, max_steps=9, n_bins=3),
+    "noise_free": W.conflict(trials=90, noise=0.0),
+}
+
+
+@pytest.mark.parametrize("name", list(LCA_CASES))
+def test_lca_fp64_parity(name):
+    w = LCA_CASES[name]
+    g, o = _both(w)
+    assert_parity(w, g, o, _correct(w))
+    if o["score"] is not None:
+        assert np.array_equal(g["score"], o["score"])  # bit-identical
+        assert np.array_equal(g["best"], o["best"])
+
+
+def test_dumps_do_not_change_aggregates():
+    w = W.grid_search(seed=3)
+    a = cm.run(w, dumps=False)
+    b = cm.run(w, dumps=True)
+    for k in ("hist", "stats", "score", "best"):
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("kind", ["ddm", "lca"])
+def test_results_independent_of_launch_shape(kind):
+    w = W.ddm(trials=20_000, seed=2) if kind == "ddm" else W.conflict(trials=3000, seed=2)
+    h = cm.Handle(0)
+    ref = cm.run(w, handle=h)
+    for rpl, sps in [(1, 1), (4, 3), (64, 16), (512, 64), (1, 64)]:
+        h.set_tuning(w["kind"], w["precision"], runs_per_lane=rpl, steps_per_sync=sps)
+        got = cm.run(w, handle=h)
+        assert np.array_equal(got["hist"], ref["hist"]), (rpl, sps)
+        assert np.array_equal(got["stats"], ref["stats"]), (rpl, sps)
+
+
+def test_ties_on_duplicated_grid():
+    grid = np.array([[0.5, 1.0], [0.5, 1.0], [1.0, 0.5], [0.5, 1.0], [1.0, 0.5], [2.0, 2.0]])
+    for seed in range(1, 6):
+        w = W.conflict(trials=27, seed=seed, noise=0.0, grid=grid, reward=1.0, cost=0.0)
+        g, o = cm.run(w), oracle.run(w)
+        assert np.array_equal(g["score"], o["score"]) and np.array_equal(g["best"], o["best"])
+        assert g["best"][1] >= 2
+
+
+@pytest.mark.parametrize("kind", ["ddm", "lca", "grid"])
+def test_fp32_steps_against_fp64_oracle(kind):
+    w = {"ddm": W.ddm(trials=100_000), "lca": W.conflict(trials=10_000),
+         "grid": W.grid_search()}[kind]
+    w32 = W.with_(w, precision=W.FP32_STEP)
+    g = cm.run(w32, dumps=True)
+    o64 = oracle.run(w, dumps=True)
+    o32 = oracle.run(w32, dumps=True)
+    T = w["trials"]
+    l1 = hist_l1(g, o64, T)
+    print(f"{kind}: histogram L1 vs FP64 oracle max {l1.max():.4f} mean {l1.mean():.4f}")
+    # paired streams: the FP32 run decides like the FP64 run almost always
+    agree = (g["run_choice"] == o64["run_choice"]).mean()
+    assert agree > 0.98, agree
+    # and like the oracle's own FP32 mode even more often
+    assert (g["run_choice"] == o32["run_choice"]).mean() >= agree - 1e-3
+    if kind == "grid":
+        # trials = 100: L1 over 200 bins is dominated by a few moved runs
+        assert l1.mean() < 0.1
+        ks = np.flatnonzero(o64["score"] == o64["score"].max())
+        assert g["best"][0] in ks or abs(g["score"].max() - o64["score"].max()) <= 1.0 / T + 1e-12
+    else:
+        assert l1.max() < 0.02
