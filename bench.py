@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (used under the profiler)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy five times (the reference "
+                         "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -79,7 +82,7 @@ def cpu_baseline(w):
         out = oracle.run(w, n_threads=threads)
         steps += oracle.run_steps(w, out)
         reps += 1
-        if time.perf_counter() - t0 > 3.0 or reps >= 5:
+        if time.perf_counter() - t0 > 1.5 or reps >= 50:
             break
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "run-timesteps/s", "cores": threads, "kind": "oracle",
@@ -96,6 +99,15 @@ def main():
     import torch
     from paper_2110_15425_amd import cm, workloads as W
 
+    if args.calibrate_copy:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}))
+        return
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)

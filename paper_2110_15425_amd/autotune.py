@@ -1,0 +1,87 @@
+"""Launch-shape autotuner for libcm sweeps.
+
+For a given workload it times the simulation kernel (HIP events that libcm
+records around it) for each candidate launch shape and keeps the fastest.
+The knobs are the ones in ``cm_tuning``: runs handed to a workgroup per lane
+(which trades occupancy against the tail of long runs) and steps between
+refills of finished lanes (which trades idle lanes against refill cost).
+Results can be persisted in a JSON cache keyed by device, kind, precision
+and a size class of the sweep, so a later process reuses them without
+re-timing.
+
+Integer outputs do not depend on the launch shape (random streams are keyed
+by run, reductions are integer), so tuning never changes results.
+"""
+import json
+import math
+import os
+
+from . import cm
+
+RUNS_PER_LANE = (1, 2, 4, 8, 16, 32)
+STEPS_PER_SYNC = (1, 2, 4, 8, 16)
+
+
+def size_class(w):
+    """Coarse key: log2 buckets of settings, trials and step cap."""
+    b = lambda v: int(math.log2(max(1, int(v))))  # noqa: E731
+    return f"S{b(w['n_settings'])}-T{b(w['trials'])}-N{b(w['max_steps'])}"
+
+
+def cache_key(w, device_name):
+    return f"{device_name}|k{int(w['kind'])}|p{int(w['precision'])}|{size_class(w)}"
+
+
+def time_shape(handle, ds, reps=3):
+    """Mean simulation-kernel milliseconds over reps launches (after one warm-up)."""
+    import torch
+    ds.launch()
+    torch.cuda.synchronize()
+    handle.profile(True)
+    for _ in range(reps):
+        ds.launch()
+    ms, n = handle.profile_read()
+    handle.profile(False)
+    return ms / max(n, 1)
+
+
+def tune(handle, w, reps=3, candidates=None, verbose=False):
+    """Time every candidate shape on workload ``w``; install and return the best
+    as (tuning dict, kernel ms, table of (rpl, sps, ms))."""
+    kind, prec = int(w["kind"]), int(w["precision"])
+    ds = cm.DeviceSweep(handle, w)
+    table = []
+    cands = candidates or [(r, s) for r in RUNS_PER_LANE for s in STEPS_PER_SYNC]
+    for rpl, sps in cands:
+        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps)
+        ms = time_shape(handle, ds, reps)
+        table.append((rpl, sps, ms))
+        if verbose:
+            print(f"  runs_per_lane {rpl:3d} steps_per_sync {sps:3d}: {ms:.4f} ms", flush=True)
+    rpl, sps, ms = min(table, key=lambda r: r[2])
+    handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps)
+    return handle.get_tuning(kind, prec), ms, table
+
+
+def tuned_handle(w, cache_path=None, device=0, **kw):
+    """A handle tuned for ``w``: from the cache when it has the key, else by
+    timing (and then stored in the cache)."""
+    import torch
+    h = cm.Handle(device)
+    name = torch.cuda.get_device_name(device)
+    key = cache_key(w, name)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if key in cache:
+        t = cache[key]
+        h.set_tuning(int(w["kind"]), int(w["precision"]), **t)
+        return h, t, None
+    t, ms, table = tune(h, w, **kw)
+    if cache_path:
+        cache[key] = t
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return h, t, table

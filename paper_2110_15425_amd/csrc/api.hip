@@ -58,7 +58,7 @@ uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
-  uint64_t drive, correct, total;
+  uint64_t drive, correct, wfrag, total;
 };
 
 Layout layout(const cm_model* m, const cm_sweep* s) {
@@ -68,6 +68,11 @@ Layout layout(const cm_model* m, const cm_sweep* s) {
   off = align_up(off + 16 * sizeof(int32_t), kWorkspaceAlign);
   L.drive = off;
   if (m->kind == CM_CONFLICT_LCA) off = align_up(off + s->n_settings * 9u * 2u * sizeof(double), kWorkspaceAlign);
+  L.wfrag = off;
+  if (m->kind == CM_RATE_RNN) {
+    const uint64_t elem = m->precision == CM_FP64 ? sizeof(double) : 2u;
+    off = align_up(off + (uint64_t)m->n_units * m->n_units * elem, kWorkspaceAlign);
+  }
   L.total = std::max<uint64_t>(off, kWorkspaceAlign);
   return L;
 }
@@ -125,7 +130,10 @@ cm_status check_model_sweep(const cm_model* m, const cm_sweep* s) {
       if (!(p[CM_RNN_DT] > 0) || !isfinite(p[CM_RNN_DT])) return fail(CM_E_INVALID, "dt must be > 0");
       if (!(p[CM_RNN_NOISE] >= 0) || !isfinite(p[CM_RNN_NOISE])) return fail(CM_E_INVALID, "noise must be >= 0");
       if (!(p[CM_RNN_THRESH] > 0)) return fail(CM_E_INVALID, "threshold must be > 0");
-      return fail(CM_E_UNSUPPORTED, "rate network kernels are not built in this library");
+      if (!isfinite(p[CM_RNN_INPUT_GAIN])) return fail(CM_E_INVALID, "input gain must be finite");
+      if (m->precision == CM_FP32_STEP)
+        return fail(CM_E_UNSUPPORTED, "rate network: use CM_FP64 or CM_BF16_PROJ");
+      break;
     default:
       return fail(CM_E_INVALID, "unknown kind %u", m->kind);
   }
@@ -174,6 +182,84 @@ struct DeviceGuard {
 
 cm_status hip_fail(hipError_t e, const char* what) {
   return fail(CM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Events around the simulation kernel when profiling is on.
+struct ProfScope {
+  cm_handle* h;
+  hipStream_t st;
+  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+  hipError_t begin() {
+    if (!h->prof) return hipSuccess;
+    hipError_t e;
+    if (h->used == h->events.size()) {
+      std::pair<hipEvent_t, hipEvent_t> p{};
+      if ((e = hipEventCreate(&p.first)) != hipSuccess) return e;
+      if ((e = hipEventCreate(&p.second)) != hipSuccess) return e;
+      h->events.push_back(p);
+    }
+    ev = &h->events[h->used++];
+    return hipEventRecord(ev->first, st);
+  }
+  hipError_t end() { return ev ? hipEventRecord(ev->second, st) : hipSuccess; }
+};
+
+cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                           char* ws, const Layout& L, hipStream_t stream) {
+  const double* p = m->params;
+  const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
+  const uint32_t n = m->n_units;
+  cm::RnnArgs a{};
+  a.trials = T;
+  a.n_settings = S;
+  a.total_runs = runs;
+  a.seed = s->seed;
+  a.max_steps = s->max_steps;
+  a.n_bins = s->n_bins;
+  a.n_signals = m->n_signals;
+  a.n_units = n;
+  a.thresh = p[CM_RNN_THRESH];
+  a.flag_eps = s->flag_eps;
+  a.dt = p[CM_RNN_DT];
+  a.b = p[CM_RNN_NOISE] * sqrt(p[CM_RNN_DT]);
+  a.gain = p[CM_RNN_INPUT_GAIN];
+  a.grid = s->grid;
+  a.wfrag = ws + L.wfrag;
+  a.R = m->weights + (uint64_t)n * n;
+  a.hist = r->hist;
+  a.stats = r->stats;
+  a.run_choice = r->run_choice;
+  a.run_step = r->run_step;
+  a.run_flag = r->run_flag;
+  a.run_state = r->run_state;
+  // 16 run slots per workgroup, two workgroups per CU
+  const uint64_t want = (runs + 15) / 16;
+  const uint32_t groups = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 2ull * h->cu_count));
+  DeviceGuard guard(h->device);
+  hipError_t e;
+  if ((e = cm::launch_zero_u64(r->hist, S * 2u * s->n_bins, stream)) != hipSuccess) return hip_fail(e, "zero hist");
+  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
+  if ((e = cm::launch_rnn_prep(m->weights, n, ws + L.wfrag, m->precision != CM_FP64, stream)) != hipSuccess)
+    return hip_fail(e, "weight fragments");
+  ProfScope prof{h, stream};
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = cm::launch_rnn(m->precision, a, groups, stream)) != hipSuccess) return hip_fail(e, "rate-network kernel");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if (s->reward != 0.0 || s->cost != 0.0) {
+    cm::ScoreArgs sa{};
+    sa.n_settings = S;
+    sa.trials = T;
+    sa.seed = s->seed;
+    sa.n_signals = m->n_signals;
+    sa.reward = s->reward;
+    sa.cost = s->cost;
+    sa.grid = s->grid;
+    sa.stats = r->stats;
+    sa.score = r->score;
+    sa.best = r->best;
+    if ((e = cm::launch_score(sa, stream)) != hipSuccess) return hip_fail(e, "score kernel");
+  }
+  return ok();
 }
 
 }  // namespace
@@ -293,6 +379,8 @@ cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
   const uint32_t B = s->n_bins;
 
+  if (m->kind == CM_RATE_RNN) return launch_rnn_sweep(h, m, s, r, ws, L, stream);
+
   // launch plan for the lane-per-run kernels
   cm::SimArgs a{};
   a.trials = T;
@@ -365,20 +453,11 @@ cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     d.correct = (int32_t*)(ws + L.correct);
     if ((e = cm::launch_drive(d, stream)) != hipSuccess) return hip_fail(e, "drive precompute");
   }
-  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
-  if (h->prof) {
-    if (h->used == h->events.size()) {
-      std::pair<hipEvent_t, hipEvent_t> p{};
-      if ((e = hipEventCreate(&p.first)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-      if ((e = hipEventCreate(&p.second)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-      h->events.push_back(p);
-    }
-    ev = &h->events[h->used++];
-    if ((e = hipEventRecord(ev->first, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  }
+  ProfScope prof{h, stream};
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_sim_lane(m->kind, m->precision, direct, a, tune.block, groups, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
-  if (ev && (e = hipEventRecord(ev->second, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if (s->reward != 0.0 || s->cost != 0.0) {
     cm::ScoreArgs sa{};
     sa.n_settings = S;

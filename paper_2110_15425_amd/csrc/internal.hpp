@@ -54,6 +54,22 @@ struct DriveArgs {
   int32_t* correct;  // [9]
 };
 
+// Arguments of the rate-network kernels.
+struct RnnArgs {
+  uint64_t trials, n_settings, total_runs, seed;
+  uint32_t max_steps, n_bins, n_signals, n_units;
+  double thresh, flag_eps, b, dt, gain;
+  const double* grid;
+  const void* wfrag;  // W in matrix-core fragment order (bf16 or fp64)
+  const double* R;    // readout weights [2][n]
+  uint64_t* hist;
+  uint64_t* stats;
+  int8_t* run_choice;
+  uint32_t* run_step;
+  uint8_t* run_flag;
+  double* run_state;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_sim_lane(int kind, int precision, bool direct, const SimArgs& a, uint32_t block,
                            uint64_t n_groups, size_t lds_bytes, hipStream_t st);
@@ -61,5 +77,7 @@ hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st);
 hipError_t launch_drive(const DriveArgs& a, hipStream_t st);
 hipError_t launch_score(const ScoreArgs& a, hipStream_t st);
+hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);
+hipError_t launch_rnn(int precision, const RnnArgs& a, uint32_t groups, hipStream_t st);
 
 }  // namespace cm

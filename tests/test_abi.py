@@ -73,6 +73,20 @@ def test_invalid_lca_shapes():
 def test_unsupported_combinations():
     assert _status(W.ddm(precision=W.BF16_PROJ)) == cm.E_UNSUPPORTED
     assert _status(W.conflict(precision=W.BF16_PROJ)) == cm.E_UNSUPPORTED
+    assert _status(W.rnn(precision=W.FP32_STEP)) == cm.E_UNSUPPORTED
+
+
+def test_rate_network_shapes():
+    assert _status(W.rnn()) == cm.OK
+    assert _status(W.rnn(precision=W.BF16_PROJ)) == cm.OK
+    for n in (64, 128, 192):
+        assert _status(W.rnn(n_units=n)) == cm.OK
+    for n in (32, 100, 320):
+        assert _status(W.rnn(n_units=n)) == cm.E_INVALID
+    w = W.rnn()
+    assert _status(W.with_(w, weights=w["weights"][:1000])) == cm.E_INVALID
+    assert cm.workspace_bytes(W.rnn()) >= 256 * 256 * 8
+    assert cm.workspace_bytes(W.rnn(precision=W.BF16_PROJ)) >= 256 * 256 * 2
 
 
 def test_bins_times_steps_bound():
