@@ -181,6 +181,19 @@ cm_status cm_launch(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
                     const cm_result *result, void *workspace, uint64_t workspace_bytes,
                     void *hip_stream);
 
+/* Several sweeps in one call, stream-ordered on hip_stream.  Entry i uses
+ * models[i], sweeps[i], results[i] and workspaces[i] (workspace_bytes[i]
+ * bytes); every entry is validated before anything is enqueued.  Sweeps of
+ * the lane-per-run kinds (DDM, conflict LCA) that share a kind and precision
+ * run in one simulation launch of up to 12 sweeps: the grid evaluation of
+ * Sec. 3.6 extended over several grids of different sizes and run lengths,
+ * so small sweeps fill the GPU together.  Results are identical to separate
+ * cm_launch calls. */
+cm_status cm_launch_batch(cm_handle *h, uint32_t n, const cm_model *models,
+                          const cm_sweep *sweeps, const cm_result *results,
+                          void *const *workspaces, const uint64_t *workspace_bytes,
+                          void *hip_stream);
+
 /* Kernel timing.  While enabled, every cm_launch brackets its simulation
  * kernel with a pair of HIP events on the launch stream.  cm_profile_read
  * waits for the recorded events, returns the summed kernel time in

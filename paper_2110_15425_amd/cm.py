@@ -23,7 +23,8 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
-           "cm_get_tuning", "cm_launch", "cm_profile", "cm_profile_read", "cm_last_error"]
+           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_profile", "cm_profile_read",
+           "cm_last_error"]
 
 
 class CmError(RuntimeError):
@@ -75,6 +76,9 @@ def lib():
         L.cm_get_tuning.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(Tuning)]
         L.cm_launch.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.POINTER(Result),
                                 C.c_void_p, C.c_uint64, C.c_void_p]
+        L.cm_launch_batch.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
+                                      C.POINTER(Result), C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_uint64), C.c_void_p]
         L.cm_profile.argtypes = [C.c_void_p, C.c_int]
         L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.cm_last_error.restype = C.c_char_p
@@ -228,6 +232,19 @@ class DeviceSweep:
             out["run_flag"] = self.run_flag.cpu().numpy()
             out["run_state"] = self.run_state.cpu().numpy()
         return out
+
+
+def launch_batch(handle, sweeps, stream=None):
+    """Enqueue several DeviceSweeps with one cm_launch_batch call."""
+    import torch
+    n = len(sweeps)
+    st = stream if stream is not None else torch.cuda.current_stream(handle.device)
+    models = (Model * n)(*[d.model for d in sweeps])
+    sws = (Sweep * n)(*[d.sweep for d in sweeps])
+    res = (Result * n)(*[d.result for d in sweeps])
+    wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
+    wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
+    check(lib().cm_launch_batch(handle.h, n, models, sws, res, wsp, wsb, C.c_void_p(st.cuda_stream)))
 
 
 _default_handle = None

@@ -204,6 +204,126 @@ struct ProfScope {
   hipError_t end() { return ev ? hipEventRecord(ev->second, st) : hipSuccess; }
 };
 
+cm_status check_launch(const cm_model* m, const cm_sweep* s, const cm_result* r, void* workspace,
+                       uint64_t workspace_bytes, Layout& L) {
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  st = check_result(m, s, r);
+  if (st != CM_OK) return st;
+  L = layout(m, s);
+  if (!workspace || !aligned(workspace, kWorkspaceAlign))
+    return fail(CM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(CM_E_BUDGET, "workspace has %llu bytes, needs %llu",
+                (unsigned long long)workspace_bytes, (unsigned long long)L.total);
+  return ok();
+}
+
+// Kernel arguments and launch shape of one lane-kernel sweep.
+cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
+                    const Layout& L, cm::SimArgs& a, uint64_t& groups, size_t& lds) {
+  const cm_tuning& tune = h->tune[m->kind][m->precision];
+  const double* p = m->params;
+  const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
+  const uint32_t B = s->n_bins;
+  a = cm::SimArgs{};
+  a.trials = T;
+  a.n_settings = S;
+  a.total_runs = runs;
+  a.seed = s->seed;
+  a.max_steps = s->max_steps;
+  a.n_bins = B;
+  a.n_signals = m->n_signals;
+  a.flag_eps = s->flag_eps;
+  a.grid = s->grid;
+  a.hist = r->hist;
+  a.stats = r->stats;
+  a.run_choice = r->run_choice;
+  a.run_step = r->run_step;
+  a.run_flag = r->run_flag;
+  a.run_state = r->run_state;
+  a.steps_per_sync = tune.steps_per_sync;
+  a.correct = (const int32_t*)(ws + L.correct);
+  if (m->kind == CM_DDM) {
+    a.dt = p[CM_DDM_DT];
+    a.drift = p[CM_DDM_DRIFT];
+    a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
+    a.thresh = p[CM_DDM_THRESH];
+    a.start = p[CM_DDM_START];
+  } else {
+    a.dt = p[CM_LCA_DT];
+    a.leak = p[CM_LCA_LEAK];
+    a.comp = p[CM_LCA_COMP];
+    a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
+    a.thresh = p[CM_LCA_THRESH];
+    a.nonneg = p[CM_LCA_NONNEG] != 0.0;
+    a.drive = (const double*)(ws + L.drive);
+  }
+  uint64_t chunk = (uint64_t)tune.block * tune.runs_per_lane;
+  chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, tune.block), kMaxChunk);
+  const size_t rec_bytes = 4u * cm::rec_words(B);
+  const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
+  bool direct = false;
+  // settings touched by one chunk: at most floor((chunk-1)/T) + 2
+  if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
+    const uint64_t fit = wmax >= 2 ? (wmax - 1) * T : 0;
+    if (fit >= tune.block) chunk = fit;
+    else direct = true;
+  }
+  a.chunk = chunk;
+  a.direct = direct ? 1u : 0u;
+  a.window = direct ? 0 : (uint32_t)std::min<uint64_t>((chunk - 1) / T + 2, S);
+  groups = (runs + chunk - 1) / chunk;
+  lds = direct ? 0 : (size_t)a.window * rec_bytes;
+  return ok();
+}
+
+// Output zero-fill and the per-sweep tables the simulation reads.
+cm_status enqueue_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws, const Layout& L,
+                       hipStream_t stream) {
+  const double* p = m->params;
+  const uint64_t S = s->n_settings;
+  hipError_t e;
+  if ((e = cm::launch_zero_u64(r->hist, S * 2u * s->n_bins, stream)) != hipSuccess) return hip_fail(e, "zero hist");
+  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
+  if (m->kind == CM_DDM) {
+    // correct response per stimulus: the upper boundary
+    if ((e = cm::launch_fill_i32((int32_t*)(ws + L.correct), 1, 1, stream)) != hipSuccess)
+      return hip_fail(e, "correct table");
+  } else if (m->kind == CM_CONFLICT_LCA) {
+    cm::DriveArgs d{};
+    d.n_settings = S;
+    d.n_signals = m->n_signals;
+    d.gain = p[CM_LCA_HID_GAIN];
+    d.bias = p[CM_LCA_HID_BIAS];
+    d.offset = p[CM_LCA_OFFSET];
+    d.weights = m->weights;
+    d.grid = s->grid;
+    d.drive = (double*)(ws + L.drive);
+    d.correct = (int32_t*)(ws + L.correct);
+    if ((e = cm::launch_drive(d, stream)) != hipSuccess) return hip_fail(e, "drive precompute");
+  }
+  return ok();
+}
+
+cm_status enqueue_score(const cm_model* m, const cm_sweep* s, const cm_result* r, hipStream_t stream) {
+  if (s->reward == 0.0 && s->cost == 0.0) return ok();
+  cm::ScoreArgs sa{};
+  sa.n_settings = s->n_settings;
+  sa.trials = s->trials;
+  sa.seed = s->seed;
+  sa.n_signals = m->n_signals;
+  sa.reward = s->reward;
+  sa.cost = s->cost;
+  sa.grid = s->grid;
+  sa.stats = r->stats;
+  sa.score = r->score;
+  sa.best = r->best;
+  hipError_t e = cm::launch_score(sa, stream);
+  if (e != hipSuccess) return hip_fail(e, "score kernel");
+  return ok();
+}
+
 cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
                            char* ws, const Layout& L, hipStream_t stream) {
   const double* p = m->params;
@@ -235,29 +355,53 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
   // 16 run slots per workgroup, two workgroups per CU
   const uint64_t want = (runs + 15) / 16;
   const uint32_t groups = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 2ull * h->cu_count));
-  DeviceGuard guard(h->device);
+  cm_status st = enqueue_prep(m, s, r, ws, L, stream);
+  if (st != CM_OK) return st;
   hipError_t e;
-  if ((e = cm::launch_zero_u64(r->hist, S * 2u * s->n_bins, stream)) != hipSuccess) return hip_fail(e, "zero hist");
-  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
   if ((e = cm::launch_rnn_prep(m->weights, n, ws + L.wfrag, m->precision != CM_FP64, stream)) != hipSuccess)
     return hip_fail(e, "weight fragments");
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_rnn(m->precision, a, groups, stream)) != hipSuccess) return hip_fail(e, "rate-network kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if (s->reward != 0.0 || s->cost != 0.0) {
-    cm::ScoreArgs sa{};
-    sa.n_settings = S;
-    sa.trials = T;
-    sa.seed = s->seed;
-    sa.n_signals = m->n_signals;
-    sa.reward = s->reward;
-    sa.cost = s->cost;
-    sa.grid = s->grid;
-    sa.stats = r->stats;
-    sa.score = r->score;
-    sa.best = r->best;
-    if ((e = cm::launch_score(sa, stream)) != hipSuccess) return hip_fail(e, "score kernel");
+  return enqueue_score(m, s, r, stream);
+}
+
+// One launch of the lane kernel over the sweeps idx[0..n) (same kind and precision).
+cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm_model* ms, const cm_sweep* ss,
+                            const cm_result* rs, void* const* wss, const Layout* Ls, const uint32_t* idx,
+                            uint32_t n, hipStream_t stream) {
+  cm::LaneBatch b{};
+  b.n = n;
+  size_t lds = 0;
+  uint64_t base = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t i = idx[k];
+    uint64_t groups = 0;
+    size_t l = 0;
+    cm_status st = plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], b.a[k], groups, l);
+    if (st != CM_OK) return st;
+    b.base[k] = base;
+    base += groups;
+    lds = std::max(lds, l);
+  }
+  b.base[n] = base;
+  if (base > 0x7FFFFFFFull) return fail(CM_E_INVALID, "batch too large for one launch");
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t i = idx[k];
+    cm_status st = enqueue_prep(&ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], stream);
+    if (st != CM_OK) return st;
+  }
+  hipError_t e;
+  ProfScope prof{h, stream};
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = cm::launch_sim_lane((int)kind, (int)prec, b, lds, stream)) != hipSuccess)
+    return hip_fail(e, "simulation kernel");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t i = idx[k];
+    cm_status st = enqueue_score(&ms[i], &ss[i], &rs[i], stream);
+    if (st != CM_OK) return st;
   }
   return ok();
 }
@@ -361,117 +505,48 @@ cm_status cm_get_tuning(cm_handle* h, uint32_t kind, uint32_t precision, cm_tuni
 
 cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
                     void* workspace, uint64_t workspace_bytes, void* hip_stream) {
+  return cm_launch_batch(h, 1, m, s, r, &workspace, &workspace_bytes, hip_stream);
+}
+
+cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
+                          const cm_result* results, void* const* workspaces,
+                          const uint64_t* workspace_bytes, void* hip_stream) {
   if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
-  cm_status st = check_model_sweep(m, s);
-  if (st != CM_OK) return st;
-  st = check_result(m, s, r);
-  if (st != CM_OK) return st;
-  const Layout L = layout(m, s);
-  if (!workspace || !aligned(workspace, kWorkspaceAlign))
-    return fail(CM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
-  if (workspace_bytes < L.total)
-    return fail(CM_E_BUDGET, "workspace has %llu bytes, needs %llu",
-                (unsigned long long)workspace_bytes, (unsigned long long)L.total);
-  const cm_tuning& tune = h->tune[m->kind][m->precision];
+  if (n < 1 || !models || !sweeps || !results || !workspaces || !workspace_bytes)
+    return fail(CM_E_INVALID, "batch needs n >= 1 and non-NULL arrays");
+  std::vector<Layout> L(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    cm_status st = check_launch(&models[i], &sweeps[i], &results[i], workspaces[i], workspace_bytes[i], L[i]);
+    if (st != CM_OK) {
+      if (n > 1) g_err = "batch entry " + std::to_string(i) + ": " + g_err;
+      return st;
+    }
+  }
   hipStream_t stream = (hipStream_t)hip_stream;
-  char* ws = (char*)workspace;
-  const double* p = m->params;
-  const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
-  const uint32_t B = s->n_bins;
-
-  if (m->kind == CM_RATE_RNN) return launch_rnn_sweep(h, m, s, r, ws, L, stream);
-
-  // launch plan for the lane-per-run kernels
-  cm::SimArgs a{};
-  a.trials = T;
-  a.n_settings = S;
-  a.total_runs = runs;
-  a.seed = s->seed;
-  a.max_steps = s->max_steps;
-  a.n_bins = B;
-  a.n_signals = m->n_signals;
-  a.flag_eps = s->flag_eps;
-  a.grid = s->grid;
-  a.hist = r->hist;
-  a.stats = r->stats;
-  a.run_choice = r->run_choice;
-  a.run_step = r->run_step;
-  a.run_flag = r->run_flag;
-  a.run_state = r->run_state;
-  a.steps_per_sync = tune.steps_per_sync;
-  a.correct = (const int32_t*)(ws + L.correct);
-  if (m->kind == CM_DDM) {
-    a.dt = p[CM_DDM_DT];
-    a.drift = p[CM_DDM_DRIFT];
-    a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
-    a.thresh = p[CM_DDM_THRESH];
-    a.start = p[CM_DDM_START];
-  } else {
-    a.dt = p[CM_LCA_DT];
-    a.leak = p[CM_LCA_LEAK];
-    a.comp = p[CM_LCA_COMP];
-    a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
-    a.thresh = p[CM_LCA_THRESH];
-    a.nonneg = p[CM_LCA_NONNEG] != 0.0;
-    a.drive = (const double*)(ws + L.drive);
-  }
-  uint64_t chunk = (uint64_t)tune.block * tune.runs_per_lane;
-  chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, tune.block), kMaxChunk);
-  const size_t rec_bytes = 4u * cm::rec_words(B);
-  const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
-  bool direct = false;
-  // settings touched by one chunk: at most floor((chunk-1)/T) + 2
-  if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
-    const uint64_t fit = wmax >= 2 ? (wmax - 1) * T : 0;
-    if (fit >= tune.block) chunk = fit;
-    else direct = true;
-  }
-  a.chunk = chunk;
-  a.window = direct ? 0 : (uint32_t)std::min<uint64_t>((chunk - 1) / T + 2, S);
-  const uint64_t groups = (runs + chunk - 1) / chunk;
-  if (groups > 0x7FFFFFFFull) return fail(CM_E_INVALID, "sweep too large for one launch");
-  const size_t lds = direct ? 0 : (size_t)a.window * rec_bytes;
-
   DeviceGuard guard(h->device);
-  hipError_t e;
-  if ((e = cm::launch_zero_u64(r->hist, S * 2u * B, stream)) != hipSuccess) return hip_fail(e, "zero hist");
-  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
-  if (m->kind == CM_DDM) {
-    // correct response per stimulus: the upper boundary
-    if ((e = cm::launch_fill_i32((int32_t*)(ws + L.correct), 1, 1, stream)) != hipSuccess)
-      return hip_fail(e, "correct table");
-  } else {
-    cm::DriveArgs d{};
-    d.n_settings = S;
-    d.n_signals = m->n_signals;
-    d.gain = p[CM_LCA_HID_GAIN];
-    d.bias = p[CM_LCA_HID_BIAS];
-    d.offset = p[CM_LCA_OFFSET];
-    d.weights = m->weights;
-    d.grid = s->grid;
-    d.drive = (double*)(ws + L.drive);
-    d.correct = (int32_t*)(ws + L.correct);
-    if ((e = cm::launch_drive(d, stream)) != hipSuccess) return hip_fail(e, "drive precompute");
-  }
-  ProfScope prof{h, stream};
-  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_sim_lane(m->kind, m->precision, direct, a, tune.block, groups, lds, stream)) != hipSuccess)
-    return hip_fail(e, "simulation kernel");
-  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if (s->reward != 0.0 || s->cost != 0.0) {
-    cm::ScoreArgs sa{};
-    sa.n_settings = S;
-    sa.trials = T;
-    sa.seed = s->seed;
-    sa.n_signals = m->n_signals;
-    sa.reward = s->reward;
-    sa.cost = s->cost;
-    sa.grid = s->grid;
-    sa.stats = r->stats;
-    sa.score = r->score;
-    sa.best = r->best;
-    if ((e = cm::launch_score(sa, stream)) != hipSuccess) return hip_fail(e, "score kernel");
-  }
+  // rate-network sweeps launch one by one; lane-kernel sweeps of one kind and
+  // precision share launches of up to kMaxBatch sweeps
+  std::vector<uint32_t> group;
+  for (uint32_t kind = 0; kind < 3; ++kind)
+    for (uint32_t prec = 0; prec < 3; ++prec) {
+      group.clear();
+      for (uint32_t i = 0; i < n; ++i)
+        if (models[i].kind == kind && models[i].precision == prec) group.push_back(i);
+      if (group.empty()) continue;
+      if (kind == CM_RATE_RNN) {
+        for (uint32_t i : group) {
+          cm_status st = launch_rnn_sweep(h, &models[i], &sweeps[i], &results[i], (char*)workspaces[i], L[i], stream);
+          if (st != CM_OK) return st;
+        }
+        continue;
+      }
+      for (size_t g0 = 0; g0 < group.size(); g0 += cm::kMaxBatch) {
+        const size_t g1 = std::min(group.size(), g0 + (size_t)cm::kMaxBatch);
+        cm_status st = launch_lane_group(h, kind, prec, models, sweeps, results, workspaces, L.data(),
+                                         group.data() + g0, (uint32_t)(g1 - g0), stream);
+        if (st != CM_OK) return st;
+      }
+    }
   return ok();
 }
 

@@ -23,6 +23,7 @@ struct SimArgs {
   double drift, start;  // DDM
   double leak, comp;    // LCA
   uint32_t nonneg;
+  uint32_t direct;  // 1: count finished runs straight into global memory
   const double* grid;
   const double* drive;     // LCA: [settings][9][2]
   const int32_t* correct;  // [stimuli]
@@ -32,6 +33,15 @@ struct SimArgs {
   uint32_t* run_step;
   uint8_t* run_flag;
   double* run_state;
+};
+
+// Up to kMaxBatch sweeps of one kind and precision in one launch.
+constexpr uint32_t kMaxBatch = 12;
+struct LaneBatch {
+  uint32_t n;
+  uint32_t pad;
+  uint64_t base[kMaxBatch + 1];  // first workgroup of each sweep; base[n] = grid size
+  SimArgs a[kMaxBatch];
 };
 
 struct ScoreArgs {
@@ -71,8 +81,8 @@ struct RnnArgs {
 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_sim_lane(int kind, int precision, bool direct, const SimArgs& a, uint32_t block,
-                           uint64_t n_groups, size_t lds_bytes, hipStream_t st);
+hipError_t launch_sim_lane(int kind, int precision, const LaneBatch& b, size_t lds_bytes,
+                           hipStream_t st);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st);
 hipError_t launch_drive(const DriveArgs& a, hipStream_t st);

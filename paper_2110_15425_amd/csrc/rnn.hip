@@ -388,7 +388,8 @@ __global__ __launch_bounds__(kRnnBlock, 2) void rnn_f64_kernel(RnnArgs a) {
 
 // W (fp64 row-major n x n) -> matrix-core fragment order.
 //  bf16: fragment (b, kb), lane l = i + 16 k4 holds W[16b + i][16kb + 4k4 + 0..3].
-//  fp64: fragment (b, kb4 = 4 bb + q), lane l = i + 16 k holds W[16b + i][16bb + 4k + q].
+//  fp64: fragment (b, kb4 = 4 bb + q), lane l = i + 16 k holds
+//        W[16b + 4 (i % 4) + i / 4][16bb + 4k + q].
 __global__ void rnn_prep_kernel(const double* W, uint32_t n, void* out, int bf16) {
   const uint32_t NB = n / 16;
   const uint64_t total = (uint64_t)n * n;
@@ -403,12 +404,16 @@ __global__ void rnn_prep_kernel(const double* W, uint32_t n, void* out, int bf16
       const double v = W[(uint64_t)(16u * b + i) * n + 16u * kb + 4u * k4 + item];
       ((__bf16*)out)[e] = (__bf16)(float)v;
     } else {
-      // e enumerates (b, kb4, lane)
+      // e enumerates (b, kb4, lane).  The fp64 16x16x4 accumulator holds row
+      // 4 reg + lane/16 in register reg of a lane, so row position i of block
+      // b stands for unit 16 b + 4 (i % 4) + i / 4: each lane then holds four
+      // consecutive units (16 b + 4 g + reg), as in the bf16 layout.
       const uint32_t lane = e & 63u;
       const uint64_t frag = e >> 6;
       const uint32_t kb4 = (uint32_t)(frag % (4u * NB)), b = (uint32_t)(frag / (4u * NB));
       const uint32_t bb = kb4 >> 2, q = kb4 & 3u, i = lane & 15u, k = lane >> 4;
-      ((double*)out)[e] = W[(uint64_t)(16u * b + i) * n + 16u * bb + 4u * k + q];
+      const uint32_t row = 16u * b + 4u * (i & 3u) + (i >> 2);
+      ((double*)out)[e] = W[(uint64_t)row * n + 16u * bb + 4u * k + q];
     }
   }
 }

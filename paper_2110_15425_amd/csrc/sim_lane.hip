@@ -39,12 +39,11 @@ __device__ __forceinline__ bool near_th(double q, double th, double eps) {
 
 // Record one finished run: LDS window (or global atomics in direct mode) and
 // optional per-run dumps.
-template <bool DIRECT>
 __device__ __forceinline__ void record(const SimArgs& a, uint32_t* lds, uint32_t s_lo,
                                        const Lane& L, const double* state, int width) {
   const uint64_t n = L.n;
   const int c = L.choice;
-  if (DIRECT) {
+  if (a.direct) {
     uint64_t* st = a.stats + (uint64_t)L.s * CM_NSTAT;
     if (c >= 0) {
       const uint32_t bin = ((L.n - 1u) * a.n_bins) / a.max_steps;
@@ -232,12 +231,17 @@ struct LCA {
   }
 };
 
-template <class M, bool DIRECT>
-__global__ __launch_bounds__(kBlock) void sim_lane_kernel(SimArgs a) {
+// One launch covers up to kMaxBatch sweeps of the same kind and precision:
+// workgroups [base[i], base[i+1]) belong to sweep i.
+template <class M>
+__global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
   uint32_t* lds = (uint32_t*)lds_u64;
   __shared__ uint32_t next;
-  const uint64_t r0 = (uint64_t)blockIdx.x * a.chunk;
+  uint32_t sw = 0;
+  while (sw + 1 < batch.n && blockIdx.x >= batch.base[sw + 1]) ++sw;
+  const SimArgs& a = batch.a[sw];
+  const uint64_t r0 = (uint64_t)(blockIdx.x - batch.base[sw]) * a.chunk;
   const uint64_t r1 = min(r0 + a.chunk, a.total_runs);
   const uint32_t len = (uint32_t)(r1 - r0);
   const uint32_t s_lo = (uint32_t)(r0 / a.trials);
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(SimArgs a) {
   const uint32_t T = (uint32_t)a.trials;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
 
-  if (!DIRECT)
+  if (!a.direct)
     for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
   if (threadIdx.x == 0) next = blockDim.x;
   __syncthreads();
@@ -271,36 +275,34 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(SimArgs a) {
     if (have && !running) {
       double st[M::kWidth];
       m.state(st);
-      record<DIRECT>(a, lds, s_lo, L, st, M::kWidth);
+      record(a, lds, s_lo, L, st, M::kWidth);
       off = atomicAdd(&next, 1u);
       have = off < len;
       if (have) setup(off);
     }
   }
-  if (!DIRECT) {
+  if (!a.direct) {
     __syncthreads();
     flush(a, lds, s_lo);
   }
 }
 
 template <class M>
-hipError_t launch_model(bool direct, const SimArgs& a, uint64_t n_groups, size_t lds,
-                        hipStream_t st) {
-  if (direct) hipLaunchKernelGGL((sim_lane_kernel<M, true>), dim3(n_groups), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((sim_lane_kernel<M, false>), dim3(n_groups), dim3(kBlock), lds, st, a);
+hipError_t launch_model(const LaneBatch& b, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((sim_lane_kernel<M>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sim_lane(int kind, int precision, bool direct, const SimArgs& a, uint32_t block,
-                           uint64_t n_groups, size_t lds_bytes, hipStream_t st) {
-  if (block != kBlock) return hipErrorInvalidValue;
+hipError_t launch_sim_lane(int kind, int precision, const LaneBatch& b, size_t lds_bytes,
+                           hipStream_t st) {
+  if (b.n < 1 || b.n > kMaxBatch) return hipErrorInvalidValue;
   if (kind == CM_DDM)
-    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(direct, a, n_groups, lds_bytes, st)
-                                : launch_model<DDM<CM_FP32_STEP>>(direct, a, n_groups, lds_bytes, st);
-  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(direct, a, n_groups, lds_bytes, st)
-                              : launch_model<LCA<CM_FP32_STEP>>(direct, a, n_groups, lds_bytes, st);
+    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, lds_bytes, st)
+                                : launch_model<DDM<CM_FP32_STEP>>(b, lds_bytes, st);
+  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, lds_bytes, st)
+                              : launch_model<LCA<CM_FP32_STEP>>(b, lds_bytes, st);
 }
 
 }  // namespace cm
