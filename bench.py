@@ -10,8 +10,15 @@ simulation with in-kernel histogram reduction, score and argmax.  Inputs
 are resident in HBM before timing starts.
 
 Two arithmetic modes are timed back to back on the same inputs:
-FP32 steps (normals and increments in float, accumulators and threshold
-tests in double) -- the headline ``value`` -- and FP64 throughout.
+"FP32 batched" -- FP32 steps (normals and increments in float, accumulators
+and threshold tests in double) with the launch shape chosen by the
+autotuner -- is the headline ``value``; "FP64 plain" is FP64 throughout with
+the default launch shape.
+
+Also measured (same JSON line): the 256-unit rate network (65,536 runs, bf16
+projections on matrix cores vs FP64), and the served mix -- Poisson arrivals
+of sweeps of all model kinds and sizes, continuously batched under a memory
+budget -- with p50/p99 latency and aggregate throughput.
 
 Printed: one JSON line.  ``roofline`` describes the simulation kernel (the
 dominant kernel) against the chip's VALU issue rate; ``cpu_baseline`` is the
@@ -37,7 +44,23 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Box-Muller pair, the two-unit update and threshold tests), counted from the
 # instruction mix of the step body and weighted by issue rate.  Derivation
 # in DESIGN.md ("Roofline accounting").
-LANE_OPS_PER_STEP = {"fp32_step": 176, "fp64": 352}
+LANE_OPS_PER_STEP = {"fp32_step": 78, "fp64": 240}
+
+# HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
+# WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
+# valid only for the kernel sources it was measured on.
+TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None}
+KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
+                  "paper_2110_15425_amd/csrc/internal.hpp")
+
+
+def sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -47,6 +70,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (used under the profiler)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no rate network, no served mix)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the served-mix arrival window")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
@@ -70,6 +97,48 @@ def time_mode(h, ds, steps, warmup):
     sim_ms, n = h.profile_read()
     h.profile(False)
     return wall_ms, sim_ms / max(n, 1)
+
+
+def rate_network(cm, W):
+    """The 256-unit rate network, 65,536 runs: bf16 projections vs FP64."""
+    import torch
+    out = {}
+    h = cm.Handle(0)
+    for name, prec in (("bf16_proj", W.BF16_PROJ), ("fp64", W.FP64)):
+        w = W.rnn(precision=prec)
+        ds = cm.DeviceSweep(h, w)
+        wall_ms, kern_ms = time_mode(h, ds, 3, 1)
+        rs = cm.run_steps(w, ds.results())
+        out[name] = {"run_steps_per_s": rs * 3 / (wall_ms / 1e3), "ms_per_sweep": wall_ms / 3,
+                     "kernel_ms": kern_ms, "run_steps": rs}
+        print(f"# rate network {name}: {wall_ms / 3:.3f} ms/sweep, {rs} run-steps",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return out
+
+
+def serving(cm, seconds):
+    """Served mix: Poisson(50/s) arrivals for `seconds`, continuously batched."""
+    import numpy as np
+
+    from paper_2110_15425_amd import serve
+    n = max(8, int(50 * seconds))
+    mix = serve.served_mix(n, rate_hz=50.0, seed=11)
+    h = cm.Handle(0)
+    warm = serve.served_mix(8, rate_hz=1e6, seed=12, max_runs=10_000)
+    serve.run_mix(h, warm)
+    done = serve.run_mix(h, mix, budget_bytes=32 << 30, n_streams=4)
+    steps = sum(cm.run_steps(r.w, r.result) for r in done)
+    t0 = min(r.arrival for r in done)
+    t1 = max(r.done for r in done)
+    summ = serve.latency_summary(done)
+    summ.update({"arrival_rate_hz": 50.0, "window_s": float(mix[-1][0]),
+                 "agg_run_steps_per_s": steps / (t1 - t0), "run_steps": int(steps),
+                 "budget_gib": 32, "streams": 4,
+                 "mean_runs_per_request": float(np.mean([r.w["n_settings"] * r.w["trials"]
+                                                         for r in done]))})
+    print(f"# serving: {summ}", file=sys.stderr, flush=True)
+    return summ
 
 
 def cpu_baseline(w):
@@ -111,11 +180,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    from paper_2110_15425_amd import autotune
+
     w64 = W.conflict(reward=1.0, cost=0.1)
     w32 = W.with_(w64, precision=W.FP32_STEP)
-    h = cm.Handle(0)
+    h_plain = cm.Handle(0)
+    h_tuned = cm.Handle(0)
+    # untimed: choose the FP32 launch shape on this device
+    tuned, _, _ = autotune.tune(h_tuned, w32, reps=2,
+                                candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
     res = {}
-    for name, w in (("fp32_step", w32), ("fp64", w64)):
+    for name, w, h in (("fp32_step", w32, h_tuned), ("fp64", w64, h_plain)):
         ds = cm.DeviceSweep(h, w)
         wall_ms, kern_ms = time_mode(h, ds, args.steps, args.warmup)
         out = ds.results()
@@ -127,6 +202,7 @@ def main():
 
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
+    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_hash() else None
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",
         "value": head["rate"],
@@ -142,14 +218,20 @@ def main():
         "data": "synthetic (seeded weights U(-2,2), Philox noise)",
         "config": {"workload": "conflict network -> LCA, 64 control settings x 10000 trials",
                    "settings": 64, "trials": 10000, "max_steps": 1000, "n_bins": 100,
-                   "score": "reward 1.0, cost 0.1", "run_steps_per_sweep": head["run_steps"]},
-        "fp64_plain": {"value": res["fp64"]["rate"], "ms_per_step": res["fp64"]["wall_ms"] / args.steps,
+                   "score": "reward 1.0, cost 0.1", "run_steps_per_sweep": head["run_steps"],
+                   "tuning": tuned},
+        "fp64_plain": {"value": res["fp64"]["rate"],
+                       "ms_per_step": res["fp64"]["wall_ms"] / args.steps,
                        "kernel_ms": res["fp64"]["kern_ms"]},
         "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": traffic,
                      "kernel": "sim_lane_kernel<LCA<FP32_STEP>>",
-                     "kernel_ms": head["kern_ms"]},
+                     "kernel_ms": head["kern_ms"],
+                     "lane_ops_per_run_step": LANE_OPS_PER_STEP["fp32_step"]},
     }
+    if not args.no_extras:
+        line["rate_network"] = rate_network(cm, W)
+        line["serving"] = serving(cm, args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w64)
     print(json.dumps(line), flush=True)

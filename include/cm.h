@@ -152,9 +152,13 @@ typedef struct {
   double *run_state;
 } cm_result;
 
-/* Launch-shape knobs; 0 in a field means "let the library choose".
+/* Launch-shape knobs; 0 in a field means "let the library choose".  The
+ * register-use versus occupancy trade-off the Distill paper measures on its
+ * GPU kernels (Sec. 6.3) is what these choose between; cm_get_tuning
+ * reports the stored values (runs_per_lane 0 = size-dependent).
  *  block          threads per workgroup (64..1024, multiple of 64).
- *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane.
+ *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane
+ *                 (0: chosen per launch from the sweep size).
  *  steps_per_sync lane-per-run kernels: steps between refills of finished
  *                 lanes (1..64).
  *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64). */

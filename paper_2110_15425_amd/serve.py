@@ -1,0 +1,212 @@
+"""Serving loop: continuous batching of simulation sweeps on one GPU.
+
+Requests (workload dicts) arrive over time.  The server admits them while
+the device-memory budget and a free stream allow, groups the admitted
+requests of one tick into batched launches (``cm_launch_batch``: sweeps of
+the same kind and precision share one simulation kernel), and puts each
+group on its own stream, so work from different requests overlaps on the
+device while earlier groups are still running.  Inputs stay resident on the
+device from admission to completion; only the small integer results come
+back, through pinned host buffers, and a request's latency is measured from
+its arrival to the moment its results are on the host.
+
+Results do not depend on what else is in flight: every random number is
+keyed by the request's own (seed, setting, trial, step) and every reduction
+is an integer sum, so a request computes the same outputs alone and in any
+mix.
+
+The scheduling core (``Scheduler``) is pure Python and device-free so it can
+be tested on the CPU; ``GpuBackend`` does the device work through libcm.
+"""
+import collections
+import time
+
+import numpy as np
+
+from . import cm, workloads as W
+
+
+def request_bytes(w):
+    """Device bytes a request holds while in flight: inputs, outputs and
+    libcm workspace."""
+    S, T, B = int(w["n_settings"]), int(w["trials"]), int(w["n_bins"])
+    nw = 0 if w.get("weights") is None else int(np.asarray(w["weights"]).size)
+    ng = 0 if int(w["n_signals"]) == 0 else S * int(w["n_signals"])
+    out = S * 2 * B * 8 + S * cm.NSTAT * 8 + S * 8 + 16
+    return 8 * (nw + ng) + out + cm.workspace_bytes(w)
+
+
+class Request:
+    __slots__ = ("rid", "w", "arrival", "admitted", "done", "result", "nbytes")
+
+    def __init__(self, rid, w, arrival):
+        self.rid, self.w, self.arrival = rid, w, arrival
+        self.admitted = self.done = None
+        self.result = None
+        self.nbytes = request_bytes(w)
+
+
+class Scheduler:
+    """Admission by memory budget and free streams; FIFO among waiting
+    requests, but a request that does not fit does not block smaller ones
+    behind it (they may pass it while it waits for memory)."""
+
+    def __init__(self, backend, budget_bytes, n_streams=4, max_group=12):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.n_streams = n_streams
+        self.max_group = max_group
+        self.waiting = collections.deque()
+        self.inflight = []  # (stream index, [requests], handle)
+        self.free_streams = list(range(n_streams))
+        self.used = 0
+        self.finished = []
+
+    def submit(self, req):
+        if req.nbytes > self.budget:
+            raise ValueError(f"request {req.rid} needs {req.nbytes} bytes, budget {self.budget}")
+        self.waiting.append(req)
+
+    def _admit(self, now):
+        if not self.free_streams or not self.waiting:
+            return
+        group, keep = [], collections.deque()
+        while self.waiting:
+            r = self.waiting.popleft()
+            if len(group) < self.max_group and self.used + r.nbytes <= self.budget:
+                self.used += r.nbytes
+                r.admitted = now
+                group.append(r)
+            else:
+                keep.append(r)
+        self.waiting = keep
+        if group:
+            si = self.free_streams.pop()
+            token = self.backend.launch(si, [r.w for r in group])
+            self.inflight.append((si, group, token))
+
+    def _reap(self, now):
+        still = []
+        for si, group, token in self.inflight:
+            results = self.backend.poll(token)
+            if results is None:
+                still.append((si, group, token))
+                continue
+            t = self.backend.clock()
+            for r, res in zip(group, results):
+                r.done = t
+                r.result = res
+                self.used -= r.nbytes
+                self.finished.append(r)
+            self.free_streams.append(si)
+        self.inflight = still
+
+    def tick(self):
+        now = self.backend.clock()
+        self._reap(now)
+        self._admit(now)
+
+    def idle(self):
+        return not self.waiting and not self.inflight
+
+    def drain(self, sleep=0.0002):
+        while not self.idle():
+            self.tick()
+            if sleep:
+                time.sleep(sleep)
+
+
+class GpuBackend:
+    """Device side of the server: one HIP stream per slot, batched launches,
+    asynchronous copies of the results into pinned host memory."""
+
+    def __init__(self, handle, n_streams=4):
+        import torch
+        self.torch = torch
+        self.h = handle
+        # all streams at the default priority
+        self.streams = [torch.cuda.Stream(device=handle.device) for _ in range(n_streams)]
+
+    @staticmethod
+    def clock():
+        return time.perf_counter()
+
+    def launch(self, si, ws):
+        torch = self.torch
+        st = self.streams[si]
+        with torch.cuda.stream(st):
+            ds = [cm.DeviceSweep(self.h, w) for w in ws]
+            cm.launch_batch(self.h, ds, stream=st)
+            host = []
+            for d in ds:
+                hh = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
+                      for k, v in (("hist", d.hist), ("stats", d.stats), ("score", d.score),
+                                   ("best", d.best)) if v is not None}
+                for k, t in hh.items():
+                    t.copy_(getattr(d, k), non_blocking=True)
+                host.append(hh)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return (ev, ds, host)
+
+    def poll(self, token):
+        ev, ds, host = token
+        if not ev.query():
+            return None
+        out = []
+        for hh in host:
+            out.append({k: (t.numpy().view(np.uint64) if k in ("hist", "stats") else t.numpy())
+                        for k, t in hh.items()})
+        return out
+
+
+def served_mix(n_requests, rate_hz=50.0, seed=11, max_runs=10 ** 6, fp32=True):
+    """The served-mix workload: Poisson arrivals at rate_hz; each request picks
+    one of the four model configurations uniformly, a log-uniform total run
+    count in [10^3, max_runs] and a grid size uniform in [1, 4096]; trials per
+    setting = max(1, round(runs / grid)).  Request i's noise seed is 1000 + i.
+    Returns [(arrival offset in s, workload)]."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    grid64 = W.control_grid(64)
+    for i in range(n_requests):
+        t += g.exponential(1.0 / rate_hz)
+        cfg = int(g.integers(0, 4))
+        runs = int(10 ** g.uniform(3.0, np.log10(max_runs)))
+        G = int(g.integers(1, 4097))
+        T = max(1, int(round(runs / G)))
+        seed_i = 1000 + i
+        if cfg == 0:
+            w = W.ddm(trials=T, seed=seed_i, drifts=np.linspace(0.0, 0.6, G),
+                      precision=W.FP32_STEP if fp32 else W.FP64)
+        elif cfg in (1, 2):
+            w = W.conflict(trials=T, seed=seed_i, grid=grid64[:G],
+                           precision=W.FP32_STEP if fp32 else W.FP64,
+                           reward=1.0 if cfg == 2 else 0.0, cost=0.1 if cfg == 2 else 0.0)
+        else:
+            w = W.rnn(trials=T, seed=seed_i, gains=np.linspace(0.5, 1.5, G),
+                      precision=W.BF16_PROJ if fp32 else W.FP64)
+        out.append((t, w))
+    return out
+
+
+def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4):
+    """Replay a served mix in real time; returns the finished requests."""
+    be = GpuBackend(handle, n_streams)
+    sch = Scheduler(be, budget_bytes, n_streams)
+    t0 = be.clock()
+    pending = collections.deque(Request(i, w, t0 + dt) for i, (dt, w) in enumerate(mix))
+    while pending or not sch.idle():
+        now = be.clock()
+        while pending and pending[0].arrival <= now:
+            sch.submit(pending.popleft())
+        sch.tick()
+        time.sleep(0.0002)
+    return sch.finished
+
+
+def latency_summary(finished):
+    lat = np.array([r.done - r.arrival for r in finished]) * 1e3
+    return dict(requests=len(lat), p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()))
