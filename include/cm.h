@@ -161,9 +161,12 @@ typedef struct {
  *                 (0: chosen per launch from the sweep size).
  *  steps_per_sync lane-per-run kernels: steps between refills of finished
  *                 lanes (1..64).
- *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64). */
+ *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64).
+ *  lanes_per_run  DDM only: 1 (one lane per run) or 64 (one wavefront per
+ *                 run, 128 steps per prefix scan; runs_per_lane then counts
+ *                 runs per wavefront). */
 typedef struct {
-  uint32_t block, runs_per_lane, steps_per_sync, tile_rows;
+  uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run;
 } cm_tuning;
 
 /* Pure host checks of a model/sweep pair; touches no device. */

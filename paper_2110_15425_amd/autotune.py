@@ -20,6 +20,7 @@ from . import cm
 
 RUNS_PER_LANE = (1, 2, 4, 8, 16, 32)
 STEPS_PER_SYNC = (1, 2, 4, 8, 16)
+RUNS_PER_WAVE = (1, 2, 4, 8, 16, 32, 64)  # DDM, one wavefront per run
 
 
 def size_class(w):
@@ -45,21 +46,32 @@ def time_shape(handle, ds, reps=3):
     return ms / max(n, 1)
 
 
+def default_candidates(w):
+    """(runs_per_lane, steps_per_sync, lanes_per_run) shapes worth timing."""
+    c = [(r, s, 1) for r in RUNS_PER_LANE for s in STEPS_PER_SYNC]
+    if int(w["kind"]) == 0:  # DDM: also one wavefront per run
+        c += [(r, 4, 64) for r in RUNS_PER_WAVE]
+    return c
+
+
 def tune(handle, w, reps=3, candidates=None, verbose=False):
     """Time every candidate shape on workload ``w``; install and return the best
-    as (tuning dict, kernel ms, table of (rpl, sps, ms))."""
+    as (tuning dict, kernel ms, table of (rpl, sps, lpr, ms))."""
     kind, prec = int(w["kind"]), int(w["precision"])
     ds = cm.DeviceSweep(handle, w)
     table = []
-    cands = candidates or [(r, s) for r in RUNS_PER_LANE for s in STEPS_PER_SYNC]
-    for rpl, sps in cands:
-        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps)
+    cands = candidates or default_candidates(w)
+    for c in cands:
+        rpl, sps = c[0], c[1]
+        lpr = c[2] if len(c) > 2 else 1
+        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr)
         ms = time_shape(handle, ds, reps)
-        table.append((rpl, sps, ms))
+        table.append((rpl, sps, lpr, ms))
         if verbose:
-            print(f"  runs_per_lane {rpl:3d} steps_per_sync {sps:3d}: {ms:.4f} ms", flush=True)
-    rpl, sps, ms = min(table, key=lambda r: r[2])
-    handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps)
+            print(f"  runs/lane {rpl:3d} steps/sync {sps:3d} lanes/run {lpr:2d}: {ms:.4f} ms",
+                  flush=True)
+    rpl, sps, lpr, ms = min(table, key=lambda r: r[3])
+    handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr)
     return handle.get_tuning(kind, prec), ms, table
 
 

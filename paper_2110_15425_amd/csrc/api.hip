@@ -165,6 +165,7 @@ cm_tuning default_tuning(uint32_t kind, uint32_t prec) {
   t.runs_per_lane = 0;
   t.steps_per_sync = kind == CM_DDM ? 4 : 16;  // DDM counts step pairs
   t.tile_rows = 64;
+  t.lanes_per_run = kind == CM_DDM ? 64 : 1;
   (void)prec;
   return t;
 }
@@ -265,16 +266,23 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   // workgroup's chunk when the sweep is large.  Measured on MI355X: 2 for
   // ~10^5-10^6 runs, 16 for ~10^7.
   uint64_t rpl = tune.runs_per_lane;
-  if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, runs / 262144));
-  uint64_t chunk = (uint64_t)tune.block * rpl;
-  chunk = std::min<uint64_t>(std::max<uint64_t>(chunk, tune.block), kMaxChunk);
+  uint64_t chunk;
+  if (m->kind == CM_DDM && tune.lanes_per_run == 64) {
+    // one wavefront per run: a workgroup of 4 wavefronts takes 4 runs per round
+    if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, runs / (32ull * h->cu_count)));
+    chunk = 4u * rpl;
+  } else {
+    if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, runs / 262144));
+    chunk = (uint64_t)tune.block * rpl;
+  }
+  chunk = std::min<uint64_t>(chunk, kMaxChunk);
   const size_t rec_bytes = 4u * cm::rec_words(B);
   const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
   bool direct = false;
   // settings touched by one chunk: at most floor((chunk-1)/T) + 2
   if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
     const uint64_t fit = wmax >= 2 ? (wmax - 1) * T : 0;
-    if (fit >= tune.block) chunk = fit;
+    if (fit >= std::min<uint64_t>(chunk, tune.block)) chunk = fit;
     else direct = true;
   }
   a.chunk = chunk;
@@ -402,7 +410,8 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   hipError_t e;
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_sim_lane((int)kind, (int)prec, b, lds, stream)) != hipSuccess)
+  const bool scan = kind == CM_DDM && h->tune[kind][prec].lanes_per_run == 64;
+  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   for (uint32_t k = 0; k < n; ++k) {
@@ -494,6 +503,9 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
   if (!v.block) v.block = d.block;
   if (!v.steps_per_sync) v.steps_per_sync = d.steps_per_sync;
   if (!v.tile_rows) v.tile_rows = d.tile_rows;
+  if (!v.lanes_per_run) v.lanes_per_run = d.lanes_per_run;
+  if (v.lanes_per_run != 1 && !(kind == CM_DDM && v.lanes_per_run == 64))
+    return fail(CM_E_INVALID, "lanes_per_run must be 1 (or 64 for the DDM)");
   if (v.block != 256) return fail(CM_E_UNSUPPORTED, "block must be 256");
   if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
   if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");

@@ -81,7 +81,7 @@ struct RnnArgs {
 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_sim_lane(int kind, int precision, const LaneBatch& b, size_t lds_bytes,
+hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
                            hipStream_t st);
 hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st);

@@ -287,6 +287,121 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   }
 }
 
+// Drift-diffusion with one wavefront per run.  Each lane draws one random
+// block -- the normals of two consecutive steps -- so a wave advances its run
+// 128 steps at a time.  The walk's state after any step is the start plus a
+// prefix sum of independent increments a + b z, so the 128 states come from
+// a wave-wide prefix scan (six shuffle rounds) and the first step that
+// leaves (-theta, theta) from one ballot.  Work per run-step stays close to
+// the lane-per-run kernel's (the random block and normals dominate both),
+// while a run's latency drops by the scan width: the reference sweep of 10^4
+// trials is only ~160 wavefronts of lane-per-run work, far too few to fill
+// the GPU, so its time is the latency of its longest runs.  The scan sums the
+// increments in a different order than the sequential update; the results
+// differ by rounding only (far below the flag distance).
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
+  extern __shared__ unsigned long long lds_u64[];
+  uint32_t* lds = (uint32_t*)lds_u64;
+  __shared__ uint32_t next;
+  uint32_t sw = 0;
+  while (sw + 1 < batch.n && blockIdx.x >= batch.base[sw + 1]) ++sw;
+  const SimArgs& a = batch.a[sw];
+  const uint64_t r0 = (uint64_t)(blockIdx.x - batch.base[sw]) * a.chunk;
+  const uint64_t r1 = min(r0 + a.chunk, a.total_runs);
+  const uint32_t len = (uint32_t)(r1 - r0);
+  const uint32_t s_lo = (uint32_t)(r0 / a.trials);
+  const uint32_t t_lo = (uint32_t)(r0 - (uint64_t)s_lo * a.trials);
+  const uint32_t T = (uint32_t)a.trials;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const int lane = threadIdx.x & 63;
+  const uint32_t N = a.max_steps;
+  const double th = a.thresh, eps = a.flag_eps;
+
+  if (!a.direct)
+    for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
+  if (threadIdx.x == 0) next = 0;
+  __syncthreads();
+
+  for (;;) {
+    uint32_t off = 0;
+    if (lane == 0) off = atomicAdd(&next, 1u);
+    off = __shfl(off, 0, 64);
+    if (off >= len) break;
+    Lane L;
+    const uint32_t local = t_lo + off;
+    L.s = s_lo + local / T;
+    L.t = local - (L.s - s_lo) * T;
+    L.target = 1;
+    L.flag = false;
+    L.choice = -1;
+    L.n = N;
+    const double drift = a.n_signals ? a.grid[(uint64_t)L.s * a.n_signals] : a.drift;
+    const double as = drift * a.dt;
+    const float af = (float)as, bf = (float)a.b;
+    double xs = a.start;  // state before the block
+    uint32_t n0 = 0;      // steps executed before the block
+    for (;;) {
+      const uint32_t s1 = n0 + 2u * (uint32_t)lane + 1u, s2 = s1 + 1u;  // this lane's steps
+      const Words w = philox((n0 >> 1) + (uint32_t)lane, L.t, L.s, 0u, k0, k1);
+      double d1, d2;
+      if (PREC == CM_FP64) {
+        double z0, z1;
+        normals64(w, z0, z1);
+        d1 = as + a.b * z0;
+        d2 = as + a.b * z1;
+      } else {
+        float z0, z1;
+        normals32(w, z0, z1);
+        d1 = (double)fmaf(bf, z0, af);
+        d2 = (double)fmaf(bf, z1, af);
+      }
+      double p = d1 + d2;  // inclusive prefix over lanes of the pair sums
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double v = __shfl_up(p, o, 64);
+        if (lane >= o) p = p + v;
+      }
+      double ex = __shfl_up(p, 1, 64);
+      ex = lane ? ex : 0.0;
+      const double x1 = (xs + ex) + d1, x2 = xs + p;
+      const bool v1 = s1 <= N, v2 = s2 <= N;
+      const bool c1 = v1 && (x1 >= th || x1 <= -th);
+      const bool c2 = v2 && (x2 >= th || x2 <= -th);
+      const uint64_t crossed = __ballot(c1 || c2);
+      uint32_t dstep = 0xFFFFFFFFu;
+      int lc = 0;
+      if (crossed) {
+        lc = __builtin_ctzll(crossed);
+        dstep = (uint32_t)__shfl((int)(c1 ? s1 : s2), lc, 64);
+      }
+      const bool f1 = v1 && s1 <= dstep && (near_th(x1, th, eps) || near_th(x1, -th, eps));
+      const bool f2 = v2 && s2 <= dstep && (near_th(x2, th, eps) || near_th(x2, -th, eps));
+      if (__ballot(f1 || f2)) L.flag = true;
+      if (crossed) {
+        xs = __shfl(c1 ? x1 : x2, lc, 64);
+        L.n = dstep;
+        L.choice = xs >= th ? 1 : 0;
+        break;
+      }
+      if (n0 + 128u >= N) {  // the cap falls in this block: undecided at step N
+        const int ln = (int)((N - n0 - 1u) >> 1);
+        xs = __shfl(((N - n0) & 1u) ? x1 : x2, ln, 64);
+        L.n = N;
+        L.choice = -1;
+        break;
+      }
+      xs = __shfl(x2, 63, 64);
+      n0 += 128u;
+    }
+    if (lane == 0) record(a, lds, s_lo, L, &xs, 1);
+  }
+  if (!a.direct) {
+    __syncthreads();
+    flush(a, lds, s_lo);
+  }
+}
+
 template <class M>
 hipError_t launch_model(const LaneBatch& b, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL((sim_lane_kernel<M>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
@@ -295,9 +410,16 @@ hipError_t launch_model(const LaneBatch& b, size_t lds, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_sim_lane(int kind, int precision, const LaneBatch& b, size_t lds_bytes,
+hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
                            hipStream_t st) {
   if (b.n < 1 || b.n > kMaxBatch) return hipErrorInvalidValue;
+  if (kind == CM_DDM && scan) {
+    if (precision == CM_FP64)
+      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP64>), dim3(b.base[b.n]), dim3(kBlock), lds_bytes, st, b);
+    else
+      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP32_STEP>), dim3(b.base[b.n]), dim3(kBlock), lds_bytes, st, b);
+    return hipGetLastError();
+  }
   if (kind == CM_DDM)
     return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, lds_bytes, st)
                                 : launch_model<DDM<CM_FP32_STEP>>(b, lds_bytes, st);

@@ -23,7 +23,7 @@ def _correct(w):
 
 def _both(w, **kw):
     print(f"case kind={w['kind']} prec={w['precision']} S={w['n_settings']} T={w['trials']} "
-          f"N={w['max_steps']} B={w['n_bins']} seed={w['seed']}", flush=True)
+          f"N={w['max_steps']} B={w['n_bins']} seed={w['seed']} {kw}", flush=True)
     g = cm.run(w, dumps=True, **kw)
     o = oracle.run(w, dumps=True)
     return g, o
@@ -43,10 +43,14 @@ DDM_CASES = {
 }
 
 
+@pytest.mark.parametrize("lanes_per_run", [64, 1])
 @pytest.mark.parametrize("name", list(DDM_CASES))
-def test_ddm_fp64_parity(name):
+def test_ddm_fp64_parity(name, lanes_per_run):
+    """One wavefront per run (prefix scan over 128 steps) and one lane per run."""
     w = DDM_CASES[name]
-    g, o = _both(w)
+    h = cm.Handle(0)
+    h.set_tuning(W.DDM, W.FP64, lanes_per_run=lanes_per_run)
+    g, o = _both(w, handle=h)
     assert_parity(w, g, o, _correct(w))
 
 
@@ -85,11 +89,14 @@ def test_results_independent_of_launch_shape(kind):
     w = W.ddm(trials=20_000, seed=2) if kind == "ddm" else W.conflict(trials=3000, seed=2)
     h = cm.Handle(0)
     ref = cm.run(w, handle=h)
-    for rpl, sps in [(1, 1), (4, 3), (64, 16), (512, 64), (1, 64)]:
-        h.set_tuning(w["kind"], w["precision"], runs_per_lane=rpl, steps_per_sync=sps)
-        got = cm.run(w, handle=h)
-        assert np.array_equal(got["hist"], ref["hist"]), (rpl, sps)
-        assert np.array_equal(got["stats"], ref["stats"]), (rpl, sps)
+    lprs = (1, 64) if kind == "ddm" else (1,)
+    for lpr in lprs:
+        for rpl, sps in [(1, 1), (4, 3), (64, 16), (512, 64), (1, 64)]:
+            h.set_tuning(w["kind"], w["precision"], runs_per_lane=rpl, steps_per_sync=sps,
+                         lanes_per_run=lpr)
+            got = cm.run(w, handle=h)
+            assert np.array_equal(got["hist"], ref["hist"]), (lpr, rpl, sps)
+            assert np.array_equal(got["stats"], ref["stats"]), (lpr, rpl, sps)
 
 
 def test_ties_on_duplicated_grid():
@@ -101,12 +108,15 @@ def test_ties_on_duplicated_grid():
         assert g["best"][1] >= 2
 
 
-@pytest.mark.parametrize("kind", ["ddm", "lca", "grid"])
+@pytest.mark.parametrize("kind", ["ddm", "ddm_lane", "lca", "grid"])
 def test_fp32_steps_against_fp64_oracle(kind):
-    w = {"ddm": W.ddm(trials=100_000), "lca": W.conflict(trials=10_000),
-         "grid": W.grid_search()}[kind]
+    w = {"ddm": W.ddm(trials=100_000), "ddm_lane": W.ddm(trials=100_000, seed=4),
+         "lca": W.conflict(trials=10_000), "grid": W.grid_search()}[kind]
     w32 = W.with_(w, precision=W.FP32_STEP)
-    g = cm.run(w32, dumps=True)
+    h = cm.Handle(0)
+    if kind == "ddm_lane":
+        h.set_tuning(W.DDM, W.FP32_STEP, lanes_per_run=1)
+    g = cm.run(w32, dumps=True, handle=h)
     o64 = oracle.run(w, dumps=True)
     o32 = oracle.run(w32, dumps=True)
     T = w["trials"]
