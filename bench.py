@@ -4,16 +4,18 @@
 Workload: the two-pathway conflict network (one-hot inputs -> logistic
 hidden layers -> 2-unit leaky competing accumulator), 64 control-gain
 settings x 10,000 trials, step cap 1000, 100-bin decision-time histograms,
-grid score with reward 1 and cost 0.1 and the best setting.  One step of the
-benchmark is one whole sweep: output zero-fill, drive precompute,
-simulation with in-kernel histogram reduction, score and argmax.  Inputs
+grid score with reward 1 and cost 0.1 and the best setting.  One sweep is:
+output zero-fill, drive precompute, simulation with in-kernel histogram
+reduction, score and argmax.  Inputs
 are resident in HBM before timing starts.
 
 Two arithmetic modes are timed back to back on the same inputs:
 "FP32 batched" -- FP32 steps (normals and increments in float, accumulators
-and threshold tests in double) with the launch shape chosen by the
-autotuner -- is the headline ``value``; "FP64 plain" is FP64 throughout with
-the default launch shape.
+and threshold tests in double), the launch shape chosen by the autotuner,
+and BATCH replicate sweeps of the workload (noise seeds 1..BATCH) in one
+batched launch per benchmark step -- is the headline ``value``; a single
+FP32 sweep per step is reported beside it, and "FP64 plain" is FP64
+throughout, one sweep per step, default launch shape.
 
 Also measured (same JSON line): the 256-unit rate network (65,536 runs, bf16
 projections on matrix cores vs FP64), and the served mix -- Poisson arrivals
@@ -45,6 +47,11 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # instruction mix of the step body and weighted by issue rate.  Derivation
 # in DESIGN.md ("Roofline accounting").
 LANE_OPS_PER_STEP = {"fp32_step": 78, "fp64": 240}
+
+# "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
+# batched launch per benchmark step, so one sweep's tail of long runs overlaps
+# the next sweep's work.
+BATCH = 8
 
 # HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
@@ -81,16 +88,26 @@ def parse():
 
 
 def time_mode(h, ds, steps, warmup):
+    """ds: one DeviceSweep (cm_launch) or a list of them (one cm_launch_batch)."""
     import torch
+
+    from paper_2110_15425_amd import cm
+
+    def launch():
+        if isinstance(ds, list):
+            cm.launch_batch(h, ds)
+        else:
+            ds.launch()
+
     for _ in range(warmup):
-        ds.launch()
+        launch()
     torch.cuda.synchronize()
     h.profile(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        ds.launch()
+        launch()
     e1.record()
     torch.cuda.synchronize()
     wall_ms = e0.elapsed_time(e1)
@@ -190,7 +207,7 @@ def main():
     tuned, _, _ = autotune.tune(h_tuned, w32, reps=2,
                                 candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
     res = {}
-    for name, w, h in (("fp32_step", w32, h_tuned), ("fp64", w64, h_plain)):
+    for name, w, h in (("fp32_single", w32, h_tuned), ("fp64", w64, h_plain)):
         ds = cm.DeviceSweep(h, w)
         wall_ms, kern_ms = time_mode(h, ds, args.steps, args.warmup)
         out = ds.results()
@@ -199,6 +216,15 @@ def main():
                          rate=rs * args.steps / (wall_ms / 1e3))
         print(f"# {name}: {wall_ms / args.steps:.4f} ms/sweep, simulation kernel "
               f"{kern_ms:.4f} ms, {rs} run-steps/sweep", file=sys.stderr, flush=True)
+    # FP32 batched: BATCH replicate sweeps (noise seeds 1..BATCH) in one launch
+    wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
+    dsb = [cm.DeviceSweep(h_tuned, w) for w in wb]
+    wall_ms, kern_ms = time_mode(h_tuned, dsb, args.steps, args.warmup)
+    rs = sum(cm.run_steps(w, d.results()) for w, d in zip(wb, dsb))
+    res["fp32_step"] = dict(run_steps=rs, wall_ms=wall_ms, kern_ms=kern_ms,
+                            rate=rs * args.steps / (wall_ms / 1e3))
+    print(f"# fp32 batched x{BATCH}: {wall_ms / args.steps:.4f} ms/step, simulation kernel "
+          f"{kern_ms:.4f} ms, {rs} run-steps/step", file=sys.stderr, flush=True)
 
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
@@ -218,8 +244,12 @@ def main():
         "data": "synthetic (seeded weights U(-2,2), Philox noise)",
         "config": {"workload": "conflict network -> LCA, 64 control settings x 10000 trials",
                    "settings": 64, "trials": 10000, "max_steps": 1000, "n_bins": 100,
-                   "score": "reward 1.0, cost 0.1", "run_steps_per_sweep": head["run_steps"],
+                   "score": "reward 1.0, cost 0.1", "sweeps_per_step": BATCH,
+                   "noise_seeds": f"1..{BATCH}", "run_steps_per_step": head["run_steps"],
                    "tuning": tuned},
+        "fp32_single_sweep": {"value": res["fp32_single"]["rate"],
+                              "ms_per_step": res["fp32_single"]["wall_ms"] / args.steps,
+                              "kernel_ms": res["fp32_single"]["kern_ms"]},
         "fp64_plain": {"value": res["fp64"]["rate"],
                        "ms_per_step": res["fp64"]["wall_ms"] / args.steps,
                        "kernel_ms": res["fp64"]["kern_ms"]},
