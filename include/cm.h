@@ -201,6 +201,20 @@ cm_status cm_launch_batch(cm_handle *h, uint32_t n, const cm_model *models,
                           void *const *workspaces, const uint64_t *workspace_bytes,
                           void *hip_stream);
 
+/* Ablation: the same sweep executed node by node, the GPU analogue of the
+ * Distill paper's per-node compilation (Sec. 6.2): each step runs as separate
+ * kernels for the random numbers, the accumulator update and the threshold
+ * test with compaction of the active runs, with run state in HBM and the host
+ * driving the step loop (it synchronises on the stream every 16 steps to
+ * stop early when no run is left).  DDM and conflict LCA only.  Results are
+ * identical to cm_launch.  The workspace must hold
+ * cm_unfused_workspace_bytes bytes (about 50 bytes per run). */
+cm_status cm_unfused_workspace_bytes(const cm_model *model, const cm_sweep *sweep,
+                                     uint64_t *bytes);
+cm_status cm_launch_unfused(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
+                            const cm_result *result, void *workspace, uint64_t workspace_bytes,
+                            void *hip_stream);
+
 /* Kernel timing.  While enabled, every cm_launch brackets its simulation
  * kernel with a pair of HIP events on the launch stream.  cm_profile_read
  * waits for the recorded events, returns the summed kernel time in

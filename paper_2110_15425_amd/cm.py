@@ -23,8 +23,8 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
-           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_profile", "cm_profile_read",
-           "cm_last_error"]
+           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_unfused_workspace_bytes",
+           "cm_launch_unfused", "cm_profile", "cm_profile_read", "cm_last_error"]
 
 
 class CmError(RuntimeError):
@@ -80,6 +80,8 @@ def lib():
         L.cm_launch_batch.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
                                       C.POINTER(Result), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_uint64), C.c_void_p]
+        L.cm_unfused_workspace_bytes.argtypes = L.cm_workspace_bytes.argtypes
+        L.cm_launch_unfused.argtypes = L.cm_launch.argtypes
         L.cm_profile.argtypes = [C.c_void_p, C.c_int]
         L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.cm_last_error.restype = C.c_char_p
@@ -214,6 +216,19 @@ class DeviceSweep:
                              ptr(self.run_step) if dumps else None,
                              ptr(self.run_flag) if dumps else None,
                              ptr(self.run_state) if dumps else None)
+
+    def launch_unfused(self, stream=None):
+        """The same sweep node by node (ablation of the fused kernels)."""
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
+        n = C.c_uint64(0)
+        check(lib().cm_unfused_workspace_bytes(C.byref(self.model), C.byref(self.sweep), C.byref(n)))
+        if getattr(self, "uf_workspace", None) is None or self.uf_workspace.numel() < n.value:
+            self.uf_workspace = torch.empty(int(n.value), dtype=torch.uint8,
+                                            device=self.workspace.device)
+        check(lib().cm_launch_unfused(self.handle.h, C.byref(self.model), C.byref(self.sweep),
+                                      C.byref(self.result), C.c_void_p(self.uf_workspace.data_ptr()),
+                                      self.uf_workspace.numel(), C.c_void_p(st.cuda_stream)))
 
     def launch(self, stream=None):
         torch = self.torch

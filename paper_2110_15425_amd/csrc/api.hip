@@ -23,6 +23,7 @@ struct cm_handle {
   size_t lds_per_block;
   cm_tuning tune[3][3];  // [kind][precision]
   // kernel timing: event pairs recorded around simulation kernels
+  uint32_t* host_count = nullptr;  // pinned, for the unfused step loop
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t used = 0;
@@ -75,6 +76,32 @@ Layout layout(const cm_model* m, const cm_sweep* s) {
   }
   L.total = std::max<uint64_t>(off, kWorkspaceAlign);
   return L;
+}
+
+struct UnfusedLayout {
+  Layout base;
+  uint64_t x, z, n, flag, choice, active, count, total;
+};
+
+UnfusedLayout unfused_layout(const cm_model* m, const cm_sweep* s) {
+  UnfusedLayout U{};
+  U.base = layout(m, s);
+  const uint64_t runs = s->n_settings * s->trials;
+  uint64_t off = U.base.total;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = off;
+    off = align_up(off + bytes, kWorkspaceAlign);
+    return at;
+  };
+  U.x = take(runs * 16u);
+  U.z = take(runs * 16u);
+  U.n = take(runs * 4u);
+  U.flag = take(runs);
+  U.choice = take(runs);
+  U.active = take(runs * 8u);
+  U.count = take(8u);
+  U.total = off;
+  return U;
 }
 
 cm_status check_model_sweep(const cm_model* m, const cm_sweep* s) {
@@ -463,6 +490,7 @@ cm_status cm_create(int device_ordinal, cm_handle** out) {
 }
 
 cm_status cm_destroy(cm_handle* h) {
+  if (h && h->host_count) (void)hipHostFree(h->host_count);
   if (h) {
     for (auto& ev : h->events) {
       (void)hipEventDestroy(ev.first);
@@ -566,6 +594,98 @@ cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, cons
       }
     }
   return ok();
+}
+
+cm_status cm_unfused_workspace_bytes(const cm_model* m, const cm_sweep* s, uint64_t* bytes) {
+  if (!bytes) return fail(CM_E_INVALID, "bytes must not be NULL");
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  if (m->kind == CM_RATE_RNN) return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
+  *bytes = unfused_layout(m, s).total;
+  return ok();
+}
+
+cm_status cm_launch_unfused(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                            void* workspace, uint64_t workspace_bytes, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  if (m->kind == CM_RATE_RNN) return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
+  if ((st = check_result(m, s, r)) != CM_OK) return st;
+  const UnfusedLayout U = unfused_layout(m, s);
+  if (!workspace || !aligned(workspace, kWorkspaceAlign))
+    return fail(CM_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < U.total)
+    return fail(CM_E_BUDGET, "workspace has %llu bytes, needs %llu", (unsigned long long)workspace_bytes,
+                (unsigned long long)U.total);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceGuard guard(h->device);
+  hipError_t e;
+  if (!h->host_count && (e = hipHostMalloc((void**)&h->host_count, sizeof(uint32_t))) != hipSuccess)
+    return hip_fail(e, "hipHostMalloc");
+  char* ws = (char*)workspace;
+  if ((st = enqueue_prep(m, s, r, ws, U.base, stream)) != CM_OK) return st;
+  const double* p = m->params;
+  cm::UnfusedArgs a{};
+  a.trials = s->trials;
+  a.n_settings = s->n_settings;
+  a.total_runs = s->n_settings * s->trials;
+  a.seed = s->seed;
+  a.max_steps = s->max_steps;
+  a.n_bins = s->n_bins;
+  a.n_signals = m->n_signals;
+  a.kind = m->kind;
+  a.flag_eps = s->flag_eps;
+  a.grid = s->grid;
+  a.correct = (const int32_t*)(ws + U.base.correct);
+  if (m->kind == CM_DDM) {
+    a.dt = p[CM_DDM_DT];
+    a.drift = p[CM_DDM_DRIFT];
+    a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
+    a.thresh = p[CM_DDM_THRESH];
+    a.start = p[CM_DDM_START];
+  } else {
+    a.dt = p[CM_LCA_DT];
+    a.leak = p[CM_LCA_LEAK];
+    a.comp = p[CM_LCA_COMP];
+    a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
+    a.thresh = p[CM_LCA_THRESH];
+    a.nonneg = p[CM_LCA_NONNEG] != 0.0;
+    a.drive = (const double*)(ws + U.base.drive);
+  }
+  a.x = (double*)(ws + U.x);
+  a.z = (double*)(ws + U.z);
+  a.n = (uint32_t*)(ws + U.n);
+  a.flag = (uint8_t*)(ws + U.flag);
+  a.choice = (int8_t*)(ws + U.choice);
+  a.active = (uint32_t*)(ws + U.active);
+  a.count = (uint32_t*)(ws + U.count);
+  a.hist = r->hist;
+  a.stats = r->stats;
+  a.run_choice = r->run_choice;
+  a.run_step = r->run_step;
+  a.run_flag = r->run_flag;
+  a.run_state = r->run_state;
+  ProfScope prof{h, stream};
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = cm::launch_uf_init(a, stream)) != hipSuccess) return hip_fail(e, "unfused init");
+  uint64_t bound = a.total_runs;
+  for (uint32_t n = 1; n <= s->max_steps; ++n) {
+    const int cur = (int)((n - 1u) & 1u);
+    if ((e = cm::launch_uf_step(a, (int)m->precision, n, cur, bound, stream)) != hipSuccess)
+      return hip_fail(e, "unfused step");
+    if (n % 16u == 0 && n < s->max_steps) {  // the host-side scheduler looks at the active count
+      if ((e = hipMemcpyAsync(h->host_count, a.count + (1 - cur), sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              stream)) != hipSuccess)
+        return hip_fail(e, "active count");
+      if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      bound = *h->host_count;
+      if (!bound) break;
+    }
+  }
+  if ((e = cm::launch_uf_reduce(a, stream)) != hipSuccess) return hip_fail(e, "unfused reduce");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return enqueue_score(m, s, r, stream);
 }
 
 }  // extern "C"

@@ -80,6 +80,30 @@ struct RnnArgs {
   double* run_state;
 };
 
+// Arguments of the node-by-node (unfused) execution.
+struct UnfusedArgs {
+  uint64_t trials, n_settings, total_runs, seed;
+  uint32_t max_steps, n_bins, n_signals, kind;
+  double thresh, flag_eps, b, dt, drift, start, leak, comp;
+  uint32_t nonneg;
+  const double* grid;
+  const double* drive;
+  const int32_t* correct;
+  double* x;       // [runs][2]
+  double* z;       // [runs][2]
+  uint32_t* n;     // [runs]
+  uint8_t* flag;   // [runs]
+  int8_t* choice;  // [runs]
+  uint32_t* active;  // [2][runs]
+  uint32_t* count;   // [2]
+  uint64_t* hist;
+  uint64_t* stats;
+  int8_t* run_choice;
+  uint32_t* run_step;
+  uint8_t* run_flag;
+  double* run_state;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
                            hipStream_t st);
@@ -89,5 +113,9 @@ hipError_t launch_drive(const DriveArgs& a, hipStream_t st);
 hipError_t launch_score(const ScoreArgs& a, hipStream_t st);
 hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);
 hipError_t launch_rnn(int precision, const RnnArgs& a, uint32_t groups, hipStream_t st);
+hipError_t launch_uf_init(const UnfusedArgs& a, hipStream_t st);
+hipError_t launch_uf_step(const UnfusedArgs& a, int precision, uint32_t n, int cur, uint64_t bound,
+                          hipStream_t st);
+hipError_t launch_uf_reduce(const UnfusedArgs& a, hipStream_t st);
 
 }  // namespace cm

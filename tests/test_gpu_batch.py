@@ -86,3 +86,23 @@ def test_graph_replay_matches_eager():
         ds.stats.fill_(-1)
         g.replay()
         _same(ds.results(), eager)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["ddm", "lca"])
+def test_unfused_equals_fused(kind, prec):
+    """The node-by-node execution computes exactly what the fused kernels do."""
+    p = W.FP64 if prec == "fp64" else W.FP32_STEP
+    w = (W.ddm(trials=3000, seed=3, drifts=np.linspace(0, 0.6, 5), precision=p) if kind == "ddm"
+         else W.grid_search(n=6, trials=300, seed=4, precision=p))
+    h = cm.Handle(0)
+    fused = cm.run(w, dumps=True, handle=h)
+    ds = cm.DeviceSweep(h, w, dumps=True)
+    ds.launch_unfused()
+    got = ds.results()
+    for k in ("hist", "stats", "score", "best", "run_choice", "run_step", "run_flag"):
+        if fused.get(k) is not None:
+            assert np.array_equal(got[k], fused[k]), k
+    # identical arithmetic: even the final states agree bit for bit (lane-per-run DDM/LCA)
+    if kind == "lca":
+        assert np.array_equal(got["run_state"], fused["run_state"])
