@@ -56,7 +56,7 @@ def ddm(trials=10_000, seed=1, drift=0.3, noise=1.0, thresh=1.0, start=0.0, dt=0
     return _base(DDM, precision, p, None, 1, 1, grid, trials, seed, max_steps, n_bins, **kw)
 
 
-def conflict_weights(weights_seed=7):
+def conflict_weights(weights_seed=11):
     """W_A, W_B [4x3] and O_A, O_B [2x4], all U(-2, 2), drawn in that order."""
     g = np.random.Generator(np.random.PCG64(weights_seed))
     WA = g.uniform(-2.0, 2.0, (4, 3))
@@ -71,7 +71,7 @@ def control_levels(n=64, hi=5.0):
     return np.array([hi * i / (n - 1) for i in range(n)], np.float64)
 
 
-def conflict(trials=10_000, seed=1, weights_seed=7, grid=None, leak=0.5, comp=1.0, noise=0.1,
+def conflict(trials=10_000, seed=1, weights_seed=11, grid=None, leak=0.5, comp=1.0, noise=0.1,
              thresh=0.8, dt=0.1, max_steps=1000, n_bins=100, hid_gain=1.0, hid_bias=-4.0,
              offset=0.0, nonneg=0.0, t0=0.0, precision=FP64, weights=None, **kw):
     """Two-pathway conflict network driving a 2-unit LCA.  ``grid`` is
@@ -94,7 +94,7 @@ def control_grid(n=64, hi=5.0):
     return np.stack([a.ravel(), b.ravel()], 1)
 
 
-def grid_search(trials=100, seed=1, weights_seed=7, n=64, reward=1.0, cost=0.1, **kw):
+def grid_search(trials=100, seed=1, weights_seed=11, n=64, reward=1.0, cost=0.1, **kw):
     return conflict(trials=trials, seed=seed, weights_seed=weights_seed, grid=control_grid(n),
                     reward=reward, cost=cost, **kw)
 

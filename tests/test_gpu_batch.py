@@ -106,3 +106,20 @@ def test_unfused_equals_fused(kind, prec):
     # identical arithmetic: even the final states agree bit for bit (lane-per-run DDM/LCA)
     if kind == "lca":
         assert np.array_equal(got["run_state"], fused["run_state"])
+
+
+def test_coarse_to_fine_search_matches_full_grid():
+    """Four rounds of a 6x6 grid (57,600 runs) find an allocation as good as
+    the best of the exhaustive 64x64 grid (409,600 runs), judged by a
+    separate high-trial evaluation of both."""
+    from paper_2110_15425_amd import refine
+    h = cm.Handle(0)
+    hist, best = refine.refine(h, refine.conflict_search(trials=400), n=6, rounds=4)
+    assert sum(r["runs"] for r in hist) == 4 * 36 * 400
+    full = cm.run(W.grid_search(precision=W.FP32_STEP), handle=h)
+    gbest = W.control_grid(64)[int(full["best"][0])]
+    evalw = W.conflict(trials=40_000, seed=99, grid=np.stack([best, gbest]), reward=1.0, cost=0.1,
+                       precision=W.FP32_STEP)
+    sc = cm.run(evalw, handle=h)["score"]
+    print("refined", best, sc[0], "full grid", gbest, sc[1], [r["score"] for r in hist])
+    assert sc[0] >= sc[1] - 0.02
