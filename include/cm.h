@@ -215,6 +215,21 @@ cm_status cm_launch_unfused(cm_handle *h, const cm_model *model, const cm_sweep 
                             const cm_result *result, void *workspace, uint64_t workspace_bytes,
                             void *hip_stream);
 
+/* Exact first-passage distribution of the discretised DDM, without sampling:
+ * the Distill paper notes the DDM has an analytical solution that can replace
+ * thousands of simulated runs (Sec. 1, Sec. 4.4).  For each setting the
+ * survivor mass of the walk x_n = x_{n-1} + a + b z on n_cells cells of
+ * (-theta, theta) is propagated with the exact Gaussian step kernel (the first
+ * step from the start point, later steps from cell centres; error O(h^2) in
+ * the cell width h), one workgroup per setting.  first_passage (DEVICE,
+ * [n_settings][2][max_steps] doubles) receives the probability of deciding
+ * for choice c (0 lower, 1 upper bound) at step n in [s][c][n-1].
+ * Propagation stops once the survivor mass is below tol (the rest is 0).
+ * Requires kind CM_DDM, noise > 0, 16 <= n_cells <= 1300; trials, seed and
+ * precision are not used. */
+cm_status cm_ddm_density(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
+                         uint32_t n_cells, double tol, double *first_passage, void *hip_stream);
+
 /* Kernel timing.  While enabled, every cm_launch brackets its simulation
  * kernel with a pair of HIP events on the launch stream.  cm_profile_read
  * waits for the recorded events, returns the summed kernel time in

@@ -70,6 +70,10 @@ def lib():
                                            C.POINTER(C.c_int32)]
         L.cmo_bf16_bits.argtypes = [C.c_double]
         L.cmo_bf16_bits.restype = C.c_uint16
+        L.cmo_ddm_density.argtypes = [C.c_double] * 4 + [C.c_int, C.c_int, C.c_double,
+                                                          C.POINTER(C.c_double),
+                                                          C.POINTER(C.c_double)]
+        L.cmo_ddm_density.restype = C.c_int
         L.cmo_state_width.argtypes = [C.POINTER(_Model)]
         L.cmo_state_width.restype = C.c_int
         _lib = L
@@ -195,6 +199,17 @@ def conflict_correct(weights, gain, bias):
     c = np.zeros(9, np.int32)
     lib().cmo_conflict_correct(_ptr(wt, C.c_double), gain, bias, _ptr(c, C.c_int32))
     return c
+
+
+def ddm_density(a, b, theta, start=0.0, cells=1000, max_steps=3000, tol=1e-15):
+    """First-passage probabilities per step, (lower[N], upper[N])."""
+    lo = np.zeros(max_steps, np.float64)
+    up = np.zeros(max_steps, np.float64)
+    rc = lib().cmo_ddm_density(a, b, theta, start, cells, max_steps, tol,
+                               _ptr(lo, C.c_double), _ptr(up, C.c_double))
+    if rc:
+        raise ValueError("oracle rejected the density request")
+    return lo, up
 
 
 def bf16_bits(v):

@@ -501,6 +501,64 @@ uint32_t cmo_trajectory(const cmo_model *m, const cmo_sweep *s, int64_t setting,
 }
 
 /* ------------------------------------------------------------------------ */
+/* First-passage distribution of the discretised DDM by propagating the      */
+/* survivor mass on M cells of (-theta, theta): the walk's transition from   */
+/* a point is Gaussian, so the mass a cell receives is a difference of       */
+/* normal CDFs at its edges and the mass absorbed is a normal tail.  The     */
+/* first step leaves the exact start point, later steps the cell centres.    */
+/* ------------------------------------------------------------------------ */
+static double Phi(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
+
+int cmo_ddm_density(double a, double b, double theta, double start, int cells, int max_steps,
+                    double tol, double *lower, double *upper) {
+  if (cells < 2 || max_steps < 1 || !(b > 0) || !(theta > 0) || !(fabs(start) < theta)) return 1;
+  const int M = cells;
+  const double h = (2.0 * theta) / (double)M;
+  double *f = malloc(sizeof(double) * (size_t)(2 * M - 1));
+  double *up = malloc(sizeof(double) * (size_t)M);
+  double *lo = malloc(sizeof(double) * (size_t)M);
+  double *mass = malloc(sizeof(double) * (size_t)M);
+  double *next = malloc(sizeof(double) * (size_t)M);
+  if (!f || !up || !lo || !mass || !next) return 2;
+  for (int d = 0; d < 2 * M - 1; ++d) {
+    double k = (double)(d - (M - 1));
+    f[d] = Phi(((k + 0.5) * h - a) / b) - Phi(((k - 0.5) * h - a) / b);
+  }
+  for (int i = 0; i < M; ++i) {
+    double c = -theta + ((double)i + 0.5) * h;
+    up[i] = Phi(-((theta - c) - a) / b);
+    lo[i] = Phi(((-theta - c) - a) / b);
+    double e0 = -theta + (double)i * h, e1 = -theta + (double)(i + 1) * h;
+    mass[i] = Phi(((e1 - start) - a) / b) - Phi(((e0 - start) - a) / b);
+  }
+  for (int n = 0; n < max_steps; ++n) lower[n] = upper[n] = 0.0;
+  upper[0] = Phi(-((theta - start) - a) / b);
+  lower[0] = Phi(((-theta - start) - a) / b);
+  for (int n = 2; n <= max_steps; ++n) {
+    double pu = 0.0, pl = 0.0;
+    for (int i = 0; i < M; ++i) {
+      pu = pu + mass[i] * up[i];
+      pl = pl + mass[i] * lo[i];
+    }
+    upper[n - 1] = pu;
+    lower[n - 1] = pl;
+    double surv = 0.0;
+    for (int j = 0; j < M; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < M; ++i) acc = acc + mass[i] * f[j - i + M - 1];
+      next[j] = acc;
+      surv = surv + acc;
+    }
+    double *t = mass;
+    mass = next;
+    next = t;
+    if (surv < tol) break;
+  }
+  free(f); free(up); free(lo); free(mass); free(next);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole sweep                                                               */
 /* ------------------------------------------------------------------------ */
 int cmo_run(const cmo_model *m, const cmo_sweep *s, cmo_result *r, int n_threads) {

@@ -96,6 +96,12 @@ void cmo_conflict_correct(const double *weights, double gain, double bias, int32
  * returns the number of executed steps, writes choice and flag. */
 uint32_t cmo_trajectory(const cmo_model *m, const cmo_sweep *s, int64_t setting,
                         uint64_t trial, double *states, int8_t *choice, uint8_t *flag);
+/* First-passage probabilities of the discretised DDM x_n = x_{n-1} + a + b z
+ * with bounds +-theta, by density propagation on `cells` cells; lower[n-1]
+ * and upper[n-1] receive the probability of a decision at step n.  Stops
+ * once the survivor mass falls below tol (remaining entries 0). */
+int cmo_ddm_density(double a, double b, double theta, double start, int cells, int max_steps,
+                    double tol, double *lower, double *upper);
 /* round-to-nearest-even double -> float -> bfloat16 bits */
 uint16_t cmo_bf16_bits(double v);
 int cmo_state_width(const cmo_model *m);

@@ -24,7 +24,7 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
            "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_unfused_workspace_bytes",
-           "cm_launch_unfused", "cm_profile", "cm_profile_read", "cm_last_error"]
+           "cm_launch_unfused", "cm_ddm_density", "cm_profile", "cm_profile_read", "cm_last_error"]
 
 
 class CmError(RuntimeError):
@@ -82,6 +82,8 @@ def lib():
                                       C.POINTER(C.c_uint64), C.c_void_p]
         L.cm_unfused_workspace_bytes.argtypes = L.cm_workspace_bytes.argtypes
         L.cm_launch_unfused.argtypes = L.cm_launch.argtypes
+        L.cm_ddm_density.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.c_uint32,
+                                     C.c_double, C.c_void_p, C.c_void_p]
         L.cm_profile.argtypes = [C.c_void_p, C.c_int]
         L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.cm_last_error.restype = C.c_char_p
@@ -262,6 +264,25 @@ def launch_batch(handle, sweeps, stream=None):
     wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
     wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
     check(lib().cm_launch_batch(handle.h, n, models, sws, res, wsp, wsb, C.c_void_p(st.cuda_stream)))
+
+
+def ddm_density(w, cells=1000, tol=1e-15, handle=None):
+    """Exact first-passage probabilities of a DDM sweep's settings on the GPU:
+    array [settings, 2 (lower, upper), max_steps]."""
+    import torch
+    h = handle or default_handle()
+    dev = torch.device("cuda", h.device)
+    grid = None
+    if int(w["n_signals"]) > 0:
+        grid = torch.as_tensor(np.ascontiguousarray(w["grid"], np.float64)).to(dev)
+    m, s, keep = structs(w, None, None if grid is None else grid.data_ptr())
+    out = torch.empty((int(w["n_settings"]), 2, int(w["max_steps"])), dtype=torch.float64,
+                      device=dev)
+    st = torch.cuda.current_stream(h.device)
+    check(lib().cm_ddm_density(h.h, C.byref(m), C.byref(s), int(cells), float(tol),
+                               C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    torch.cuda.synchronize(h.device)
+    return out.cpu().numpy()
 
 
 _default_handle = None

@@ -688,4 +688,39 @@ cm_status cm_launch_unfused(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   return enqueue_score(m, s, r, stream);
 }
 
+cm_status cm_ddm_density(cm_handle* h, const cm_model* m, const cm_sweep* s, uint32_t n_cells, double tol,
+                         double* first_passage, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  if (m->kind != CM_DDM) return fail(CM_E_UNSUPPORTED, "density propagation applies to the DDM only");
+  if (!(m->params[CM_DDM_NOISE] > 0)) return fail(CM_E_INVALID, "density propagation needs noise > 0");
+  if (n_cells < 16 || n_cells > 1300) return fail(CM_E_INVALID, "n_cells must be in [16, 1300]");
+  if (s->n_settings > 0x7FFFFFFFull) return fail(CM_E_INVALID, "too many settings for one launch");
+  if (!(tol >= 0) || !isfinite(tol)) return fail(CM_E_INVALID, "tol must be finite and >= 0");
+  if (!first_passage || !aligned(first_passage, 8)) return fail(CM_E_INVALID, "first_passage must be 8-byte aligned");
+  const double* p = m->params;
+  cm::DensityArgs a{};
+  a.n_settings = s->n_settings;
+  a.max_steps = s->max_steps;
+  a.cells = n_cells;
+  a.n_signals = m->n_signals;
+  a.dt = p[CM_DDM_DT];
+  a.drift = p[CM_DDM_DRIFT];
+  a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
+  a.thresh = p[CM_DDM_THRESH];
+  a.start = p[CM_DDM_START];
+  a.tol = tol;
+  a.grid = s->grid;
+  a.out = first_passage;
+  DeviceGuard guard(h->device);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  ProfScope prof{h, stream};
+  hipError_t e;
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = cm::launch_ddm_density(a, stream)) != hipSuccess) return hip_fail(e, "density kernel");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return ok();
+}
+
 }  // extern "C"

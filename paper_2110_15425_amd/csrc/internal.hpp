@@ -104,6 +104,15 @@ struct UnfusedArgs {
   double* run_state;
 };
 
+// Arguments of the DDM density propagation.
+struct DensityArgs {
+  uint64_t n_settings;
+  uint32_t max_steps, cells, n_signals;
+  double dt, drift, b, thresh, start, tol;
+  const double* grid;
+  double* out;  // [settings][2][max_steps]
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
                            hipStream_t st);
@@ -117,5 +126,6 @@ hipError_t launch_uf_init(const UnfusedArgs& a, hipStream_t st);
 hipError_t launch_uf_step(const UnfusedArgs& a, int precision, uint32_t n, int cur, uint64_t bound,
                           hipStream_t st);
 hipError_t launch_uf_reduce(const UnfusedArgs& a, hipStream_t st);
+hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st);
 
 }  // namespace cm

@@ -135,3 +135,40 @@ def test_flag_marks_near_threshold_runs():
     # with the default epsilon a flag is rare (expected ~1e-8 per run)
     out = oracle.run(W.ddm(trials=20_000))
     assert out["stats"][0, oracle.ST["flagged"]] == 0
+
+
+# --- the oracle's density propagation (the exact first-passage distribution) ---
+
+def test_density_oracle_against_independent_propagation_and_closed_form(density):
+    lo, up = oracle.ddm_density(0.3 * 0.01, 0.1, 1.0, cells=1000, max_steps=3000)
+    u2, l2 = density  # scipy/numpy implementation in tests/pins.py
+    np.testing.assert_allclose(up, u2, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(lo, l2, rtol=0, atol=1e-14)
+    assert up.sum() + lo.sum() == pytest.approx(1.0, abs=1e-12)
+    p_err, mean_dt = pins.ddm_bgk(0.3, 1.0, 1.0, 0.01)
+    n = np.arange(1, 3001)
+    assert lo.sum() == pytest.approx(p_err, abs=2e-4)
+    assert ((up + lo) * n).sum() * 0.01 == pytest.approx(mean_dt, abs=5e-3)
+
+
+def test_density_oracle_matches_monte_carlo_oracle():
+    """Biased start and negative drift: the density's binned probabilities
+    explain the Monte-Carlo oracle's 2*10^5-trial histogram."""
+    a, b, th, x0 = -0.1 * 0.02, 0.8 * math.sqrt(0.02), 0.7, 0.2
+    lo, up = oracle.ddm_density(a, b, th, start=x0, cells=700, max_steps=600)
+    w = W.ddm(trials=200_000, seed=8, drift=-0.1, noise=0.8, thresh=0.7, start=0.2, dt=0.02,
+              max_steps=600, n_bins=60)
+    out = oracle.run(w, n_threads=8)
+    exp = np.concatenate([pins.binned(lo, 60, 600), pins.binned(up, 60, 600),
+                          [max(0.0, 1 - lo.sum() - up.sum())]])
+    obs = np.concatenate([out["hist"][0, 0], out["hist"][0, 1], [out["stats"][0, 2]]])
+    assert pins.chisq_pvalue(obs, exp) > 1e-4
+
+
+def test_density_oracle_early_stop_and_rejects():
+    lo, up = oracle.ddm_density(0.05, 0.2, 0.5, cells=200, max_steps=2000, tol=1e-12)
+    last = np.flatnonzero(up + lo)[-1]
+    assert last < 1999 and np.all(up[last + 1:] == 0) and np.all(lo[last + 1:] == 0)
+    assert up.sum() + lo.sum() == pytest.approx(1.0, abs=1e-11)
+    with pytest.raises(ValueError):
+        oracle.ddm_density(0.0, 0.0, 1.0)  # no noise: no density
