@@ -303,7 +303,6 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];
   uint32_t* lds = (uint32_t*)lds_u64;
-  __shared__ uint32_t next;
   uint32_t sw = 0;
   while (sw + 1 < batch.n && blockIdx.x >= batch.base[sw + 1]) ++sw;
   const SimArgs& a = batch.a[sw];
@@ -320,14 +319,14 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
 
   if (!a.direct)
     for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
-  if (threadIdx.x == 0) next = 0;
   __syncthreads();
 
-  for (;;) {
-    uint32_t off = 0;
-    if (lane == 0) off = atomicAdd(&next, 1u);
-    off = __shfl(off, 0, 64);
-    if (off >= len) break;
+  // The four wavefronts take the chunk's runs round-robin.  Every loop exit
+  // depends only on wave-uniform values (scalar registers), so each loop is
+  // left by the whole wavefront at once and needs no per-lane bookkeeping.
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t nwave = blockDim.x >> 6;
+  for (uint32_t off = wave; off < len; off += nwave) {
     Lane L;
     const uint32_t local = t_lo + off;
     L.s = s_lo + local / T;
@@ -372,8 +371,8 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
       uint32_t dstep = 0xFFFFFFFFu;
       int lc = 0;
       if (crossed) {
-        lc = __builtin_ctzll(crossed);
-        dstep = (uint32_t)__shfl((int)(c1 ? s1 : s2), lc, 64);
+        lc = (int)__builtin_ctzll(crossed);
+        dstep = __builtin_amdgcn_readfirstlane((uint32_t)__shfl((int)(c1 ? s1 : s2), lc, 64));
       }
       const bool f1 = v1 && s1 <= dstep && (near_th(x1, th, eps) || near_th(x1, -th, eps));
       const bool f2 = v2 && s2 <= dstep && (near_th(x2, th, eps) || near_th(x2, -th, eps));
