@@ -30,10 +30,23 @@ def reduce_dumps(w, d, correct, exclude=None):
     return hist, stats
 
 
+def lca_growth(w):
+    """Per-step growth factor of the LCA's difference mode x0 - x1:
+    1 + dt (comp - leak) (the mode is unstable when comp > leak)."""
+    p = w["params"]
+    dt, leak, comp = p[0], p[1], p[2]
+    return 1.0 + dt * max(0.0, comp - leak)
+
+
 def assert_parity(w, g, o, correct, state_rtol=1e-9, state_atol=1e-12, max_flag_frac=1e-4):
     """FP64 acceptance: per-run integers bit-exact on runs neither side
     flagged, final states within state_rtol, aggregate integers exact when
-    nothing is flagged (else exact after removing the flagged runs)."""
+    nothing is flagged (else exact after removing the flagged runs).
+
+    The two sides' normals may differ in the last bit (different libm), and
+    the LCA's difference mode amplifies such differences by lca_growth()
+    per step, so for the LCA the state tolerance grows as 1e-13 * growth^n
+    for a run of n steps (1e-13: a few hundred ulps at unit scale)."""
     flagged = (g["run_flag"] != 0) | (o["run_flag"] != 0)
     ok = ~flagged
     frac = flagged.mean()
@@ -42,8 +55,14 @@ def assert_parity(w, g, o, correct, state_rtol=1e-9, state_atol=1e-12, max_flag_
     assert bad.size == 0, (f"{bad.size} unflagged runs differ; first {bad[:5]}: gpu "
                            f"{g['run_choice'][bad[:5]]}/{g['run_step'][bad[:5]]} oracle "
                            f"{o['run_choice'][bad[:5]]}/{o['run_step'][bad[:5]]}")
-    np.testing.assert_allclose(g["run_state"][ok], o["run_state"][ok], rtol=state_rtol,
-                               atol=state_atol)
+    if int(w["kind"]) == 1:
+        amp = lca_growth(w) ** o["run_step"][ok].astype(np.float64)
+        tol = np.maximum(state_atol, 1e-13 * amp)[:, None] + state_rtol * np.abs(o["run_state"][ok])
+        diff = np.abs(g["run_state"][ok] - o["run_state"][ok])
+        assert np.all(diff <= tol), f"max state excess {np.max(diff - tol)}"
+    else:
+        np.testing.assert_allclose(g["run_state"][ok], o["run_state"][ok], rtol=state_rtol,
+                                   atol=state_atol)
     # each side's aggregates are the reduction of its own per-run outcomes
     gh, gs = reduce_dumps(w, g, correct)
     assert np.array_equal(gh, g["hist"]) and np.array_equal(gs, g["stats"])
