@@ -56,7 +56,8 @@ BATCH = 8
 # HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
 # valid only for the kernel sources it was measured on.
-TRAFFIC = {"sources_sha256": None, "bytes_per_launch": None}
+TRAFFIC = {"sources_sha256": "15245ae801b864d410c34a6925ac91a5e85ecb3356eaca74c8020d33625415f3",
+           "bytes_per_launch": 4484301}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/internal.hpp")
 
@@ -204,8 +205,9 @@ def main():
     h_plain = cm.Handle(0)
     h_tuned = cm.Handle(0)
     # untimed: choose the FP32 launch shape on this device
-    tuned, _, _ = autotune.tune(h_tuned, w32, reps=2,
-                                candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
+    wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
+    tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
+                                candidates=[(r, s) for r in (1, 2, 4, 8) for s in (4, 8, 16, 32)])
     res = {}
     for name, w, h in (("fp32_single", w32, h_tuned), ("fp64", w64, h_plain)):
         ds = cm.DeviceSweep(h, w)
@@ -217,7 +219,6 @@ def main():
         print(f"# {name}: {wall_ms / args.steps:.4f} ms/sweep, simulation kernel "
               f"{kern_ms:.4f} ms, {rs} run-steps/sweep", file=sys.stderr, flush=True)
     # FP32 batched: BATCH replicate sweeps (noise seeds 1..BATCH) in one launch
-    wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
     dsb = [cm.DeviceSweep(h_tuned, w) for w in wb]
     wall_ms, kern_ms = time_mode(h_tuned, dsb, args.steps, args.warmup)
     rs = sum(cm.run_steps(w, d.results()) for w, d in zip(wb, dsb))

@@ -162,9 +162,11 @@ typedef struct {
  *  steps_per_sync lane-per-run kernels: steps between refills of finished
  *                 lanes (1..64).
  *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64).
- *  lanes_per_run  DDM only: 1 (one lane per run) or 64 (one wavefront per
+ *  lanes_per_run  DDM only: 1 (one lane per run), 64 (one wavefront per
  *                 run, 128 steps per prefix scan; runs_per_lane then counts
- *                 runs per wavefront). */
+ *                 runs per wavefront) or 0 (per launch: 64 when every sweep
+ *                 of the launch has at most 2^20 runs, else 1).  Results do
+ *                 not depend on this choice. */
 typedef struct {
   uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run;
 } cm_tuning;

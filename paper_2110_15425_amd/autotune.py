@@ -34,13 +34,21 @@ def cache_key(w, device_name):
 
 
 def time_shape(handle, ds, reps=3):
-    """Mean simulation-kernel milliseconds over reps launches (after one warm-up)."""
+    """Mean simulation-kernel milliseconds over reps launches (after one
+    warm-up); ``ds`` is a DeviceSweep or a list of them (one batched launch)."""
     import torch
-    ds.launch()
+
+    def launch():
+        if isinstance(ds, list):
+            cm.launch_batch(handle, ds)
+        else:
+            ds.launch()
+
+    launch()
     torch.cuda.synchronize()
     handle.profile(True)
     for _ in range(reps):
-        ds.launch()
+        launch()
     ms, n = handle.profile_read()
     handle.profile(False)
     return ms / max(n, 1)
@@ -55,10 +63,14 @@ def default_candidates(w):
 
 
 def tune(handle, w, reps=3, candidates=None, verbose=False):
-    """Time every candidate shape on workload ``w``; install and return the best
-    as (tuning dict, kernel ms, table of (rpl, sps, lpr, ms))."""
+    """Time every candidate shape on workload ``w`` (a workload dict, or a list
+    of workloads of one kind and precision timed as one batched launch);
+    install and return the best as (tuning dict, kernel ms, table of
+    (rpl, sps, lpr, ms))."""
+    ws = w if isinstance(w, list) else [w]
+    w = ws[0]
     kind, prec = int(w["kind"]), int(w["precision"])
-    ds = cm.DeviceSweep(handle, w)
+    ds = [cm.DeviceSweep(handle, x) for x in ws] if len(ws) > 1 else cm.DeviceSweep(handle, w)
     table = []
     cands = candidates or default_candidates(w)
     for c in cands:

@@ -192,7 +192,7 @@ cm_tuning default_tuning(uint32_t kind, uint32_t prec) {
   t.runs_per_lane = 0;
   t.steps_per_sync = kind == CM_DDM ? 4 : 16;  // DDM counts step pairs
   t.tile_rows = 64;
-  t.lanes_per_run = kind == CM_DDM ? 64 : 1;
+  t.lanes_per_run = 0;  // DDM: chosen per launch (see plan_lane)
   (void)prec;
   return t;
 }
@@ -248,9 +248,18 @@ cm_status check_launch(const cm_model* m, const cm_sweep* s, const cm_result* r,
   return ok();
 }
 
+// The DDM's wavefront-per-run scan cuts a run's latency 64-fold at similar
+// work per step; it wins while the sweep is too small to fill the GPU with
+// lanes (measured on MI355X: 16x faster at 10^4 runs, 1.4x slower at 10^7).
+bool scan_ddm(const cm_tuning& t, uint64_t runs) {
+  if (t.lanes_per_run == 64) return true;
+  if (t.lanes_per_run == 1) return false;
+  return runs <= (1ull << 20);
+}
+
 // Kernel arguments and launch shape of one lane-kernel sweep.
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
-                    const Layout& L, cm::SimArgs& a, uint64_t& groups, size_t& lds) {
+                    const Layout& L, bool scan, cm::SimArgs& a, uint64_t& groups, size_t& lds) {
   const cm_tuning& tune = h->tune[m->kind][m->precision];
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
@@ -294,7 +303,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   // ~10^5-10^6 runs, 16 for ~10^7.
   uint64_t rpl = tune.runs_per_lane;
   uint64_t chunk;
-  if (m->kind == CM_DDM && tune.lanes_per_run == 64) {
+  if (scan) {
     // one wavefront per run: a workgroup of 4 wavefronts takes 4 runs per round
     if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, runs / (32ull * h->cu_count)));
     chunk = 4u * rpl;
@@ -413,6 +422,12 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
 cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm_model* ms, const cm_sweep* ss,
                             const cm_result* rs, void* const* wss, const Layout* Ls, const uint32_t* idx,
                             uint32_t n, hipStream_t stream) {
+  // one form per launch: the DDM scan form when every sweep of the group is small
+  bool scan = kind == CM_DDM;
+  for (uint32_t k = 0; k < n && scan; ++k) {
+    const uint32_t i = idx[k];
+    scan = scan_ddm(h->tune[kind][prec], ss[i].n_settings * ss[i].trials);
+  }
   cm::LaneBatch b{};
   b.n = n;
   size_t lds = 0;
@@ -421,7 +436,8 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     const uint32_t i = idx[k];
     uint64_t groups = 0;
     size_t l = 0;
-    cm_status st = plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], b.a[k], groups, l);
+    cm_status st =
+        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, b.a[k], groups, l);
     if (st != CM_OK) return st;
     b.base[k] = base;
     base += groups;
@@ -437,7 +453,6 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   hipError_t e;
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  const bool scan = kind == CM_DDM && h->tune[kind][prec].lanes_per_run == 64;
   if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -531,9 +546,8 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
   if (!v.block) v.block = d.block;
   if (!v.steps_per_sync) v.steps_per_sync = d.steps_per_sync;
   if (!v.tile_rows) v.tile_rows = d.tile_rows;
-  if (!v.lanes_per_run) v.lanes_per_run = d.lanes_per_run;
-  if (v.lanes_per_run != 1 && !(kind == CM_DDM && v.lanes_per_run == 64))
-    return fail(CM_E_INVALID, "lanes_per_run must be 1 (or 64 for the DDM)");
+  if (v.lanes_per_run != 0 && v.lanes_per_run != 1 && !(kind == CM_DDM && v.lanes_per_run == 64))
+    return fail(CM_E_INVALID, "lanes_per_run must be 0, 1 (or 64 for the DDM)");
   if (v.block != 256) return fail(CM_E_UNSUPPORTED, "block must be 256");
   if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
   if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");
