@@ -207,9 +207,12 @@ def main():
     # untimed: choose the FP32 launch shape on this device
     wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
     tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
-                                candidates=[(r, s) for r in (1, 2, 4, 8) for s in (4, 8, 16, 32)])
+                                candidates=[(r, s) for r in (2, 4, 8, 16, 32) for s in (4, 8, 16, 32)])
+    h_single = cm.Handle(0)
+    autotune.tune(h_single, w32, reps=2,
+                  candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
     res = {}
-    for name, w, h in (("fp32_single", w32, h_tuned), ("fp64", w64, h_plain)):
+    for name, w, h in (("fp32_single", w32, h_single), ("fp64", w64, h_plain)):
         ds = cm.DeviceSweep(h, w)
         wall_ms, kern_ms = time_mode(h, ds, args.steps, args.warmup)
         out = ds.results()

@@ -19,7 +19,7 @@ import os
 from . import cm
 
 RUNS_PER_LANE = (1, 2, 4, 8, 16, 32)
-STEPS_PER_SYNC = (1, 2, 4, 8, 16)
+STEPS_PER_SYNC = (2, 4, 8, 16, 32)
 RUNS_PER_WAVE = (1, 2, 4, 8, 16, 32, 64)  # DDM, one wavefront per run
 
 

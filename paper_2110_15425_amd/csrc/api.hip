@@ -258,8 +258,11 @@ bool scan_ddm(const cm_tuning& t, uint64_t runs) {
 }
 
 // Kernel arguments and launch shape of one lane-kernel sweep.
+// launch_runs: runs of every sweep in the same launch (sets the automatic
+// runs per lane, which trades GPU fill against the tail of each chunk).
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
-                    const Layout& L, bool scan, cm::SimArgs& a, uint64_t& groups, size_t& lds) {
+                    const Layout& L, bool scan, uint64_t launch_runs, cm::SimArgs& a,
+                    uint64_t& groups, size_t& lds) {
   const cm_tuning& tune = h->tune[m->kind][m->precision];
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
@@ -271,6 +274,8 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   a.seed = s->seed;
   a.max_steps = s->max_steps;
   a.n_bins = B;
+  a.trials_magic = cm::udiv_magic_for((uint32_t)T);
+  a.steps_magic = cm::udiv_magic_for(s->max_steps);
   a.n_signals = m->n_signals;
   a.flag_eps = s->flag_eps;
   a.grid = s->grid;
@@ -297,9 +302,9 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     a.nonneg = p[CM_LCA_NONNEG] != 0.0;
     a.drive = (const double*)(ws + L.drive);
   }
-  // Few runs per lane keep every SIMD busy when the sweep is small (the tail
+  // Few runs per lane keep every SIMD busy when the launch is small (the tail
   // of long runs dominates); many runs per lane amortise the end of each
-  // workgroup's chunk when the sweep is large.  Measured on MI355X: 2 for
+  // workgroup's chunk when the launch is large.  Measured on MI355X: 2 for
   // ~10^5-10^6 runs, 16 for ~10^7.
   uint64_t rpl = tune.runs_per_lane;
   uint64_t chunk;
@@ -308,7 +313,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, runs / (32ull * h->cu_count)));
     chunk = 4u * rpl;
   } else {
-    if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, runs / 262144));
+    if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, launch_runs / (1024ull * h->cu_count)));
     chunk = (uint64_t)tune.block * rpl;
   }
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
@@ -330,36 +335,52 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
 }
 
 // Output zero-fill and the per-sweep tables the simulation reads.
-cm_status enqueue_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws, const Layout& L,
-                       hipStream_t stream) {
-  const double* p = m->params;
+// Preparation of one sweep as item k of a batched prep launch.
+void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws, const Layout& L,
+               cm::PrepBatch& b) {
+  cm::PrepItem& it = b.it[b.n];
   const uint64_t S = s->n_settings;
-  hipError_t e;
-  if ((e = cm::launch_zero_u64(r->hist, S * 2u * s->n_bins, stream)) != hipSuccess) return hip_fail(e, "zero hist");
-  if ((e = cm::launch_zero_u64(r->stats, S * CM_NSTAT, stream)) != hipSuccess) return hip_fail(e, "zero stats");
+  const double* p = m->params;
+  it = cm::PrepItem{};
+  it.hist = r->hist;
+  it.n_hist = S * 2u * s->n_bins;
+  it.stats = r->stats;
+  it.n_stats = S * CM_NSTAT;
+  it.kind = (uint32_t)m->kind;
+  uint64_t tables = 0;
   if (m->kind == CM_DDM) {
-    // correct response per stimulus: the upper boundary
-    if ((e = cm::launch_fill_i32((int32_t*)(ws + L.correct), 1, 1, stream)) != hipSuccess)
-      return hip_fail(e, "correct table");
+    it.d.correct = (int32_t*)(ws + L.correct);
+    tables = 1;
   } else if (m->kind == CM_CONFLICT_LCA) {
-    cm::DriveArgs d{};
-    d.n_settings = S;
-    d.n_signals = m->n_signals;
-    d.gain = p[CM_LCA_HID_GAIN];
-    d.bias = p[CM_LCA_HID_BIAS];
-    d.offset = p[CM_LCA_OFFSET];
-    d.weights = m->weights;
-    d.grid = s->grid;
-    d.drive = (double*)(ws + L.drive);
-    d.correct = (int32_t*)(ws + L.correct);
-    if ((e = cm::launch_drive(d, stream)) != hipSuccess) return hip_fail(e, "drive precompute");
+    it.d.n_settings = S;
+    it.d.n_signals = m->n_signals;
+    it.d.gain = p[CM_LCA_HID_GAIN];
+    it.d.bias = p[CM_LCA_HID_BIAS];
+    it.d.offset = p[CM_LCA_OFFSET];
+    it.d.weights = m->weights;
+    it.d.grid = s->grid;
+    it.d.drive = (double*)(ws + L.drive);
+    it.d.correct = (int32_t*)(ws + L.correct);
+    tables = 9 + S * 9u;
   }
-  return ok();
+  it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + tables;
+  ++b.n;
 }
 
-cm_status enqueue_score(const cm_model* m, const cm_sweep* s, const cm_result* r, hipStream_t stream) {
-  if (s->reward == 0.0 && s->cost == 0.0) return ok();
-  cm::ScoreArgs sa{};
+cm_status enqueue_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws, const Layout& L,
+                       hipStream_t stream) {
+  cm::PrepBatch b{};
+  fill_prep(m, s, r, ws, L, b);
+  hipError_t e = cm::launch_prep(b, stream);
+  return e == hipSuccess ? ok() : hip_fail(e, "sweep preparation");
+}
+
+// Score of one sweep as the next entry of a batched score launch (unscored
+// sweeps add nothing).
+void fill_score(const cm_model* m, const cm_sweep* s, const cm_result* r, cm::ScoreBatch& b) {
+  if (s->reward == 0.0 && s->cost == 0.0) return;
+  cm::ScoreArgs& sa = b.a[b.n++];
+  sa = cm::ScoreArgs{};
   sa.n_settings = s->n_settings;
   sa.trials = s->trials;
   sa.seed = s->seed;
@@ -370,9 +391,13 @@ cm_status enqueue_score(const cm_model* m, const cm_sweep* s, const cm_result* r
   sa.stats = r->stats;
   sa.score = r->score;
   sa.best = r->best;
-  hipError_t e = cm::launch_score(sa, stream);
-  if (e != hipSuccess) return hip_fail(e, "score kernel");
-  return ok();
+}
+
+cm_status enqueue_score(const cm_model* m, const cm_sweep* s, const cm_result* r, hipStream_t stream) {
+  cm::ScoreBatch b{};
+  fill_score(m, s, r, b);
+  hipError_t e = cm::launch_score(b, stream);
+  return e == hipSuccess ? ok() : hip_fail(e, "score kernel");
 }
 
 cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
@@ -428,6 +453,8 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     const uint32_t i = idx[k];
     scan = scan_ddm(h->tune[kind][prec], ss[i].n_settings * ss[i].trials);
   }
+  uint64_t launch_runs = 0;
+  for (uint32_t k = 0; k < n; ++k) launch_runs += ss[idx[k]].n_settings * ss[idx[k]].trials;
   cm::LaneBatch b{};
   b.n = n;
   size_t lds = 0;
@@ -437,7 +464,7 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     uint64_t groups = 0;
     size_t l = 0;
     cm_status st =
-        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, b.a[k], groups, l);
+        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, launch_runs, b.a[k], groups, l);
     if (st != CM_OK) return st;
     b.base[k] = base;
     base += groups;
@@ -445,22 +472,21 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   }
   b.base[n] = base;
   if (base > 0x7FFFFFFFull) return fail(CM_E_INVALID, "batch too large for one launch");
+  cm::PrepBatch pb{};
+  cm::ScoreBatch sb{};
   for (uint32_t k = 0; k < n; ++k) {
     const uint32_t i = idx[k];
-    cm_status st = enqueue_prep(&ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], stream);
-    if (st != CM_OK) return st;
+    fill_prep(&ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], pb);
+    fill_score(&ms[i], &ss[i], &rs[i], sb);
   }
   hipError_t e;
+  if ((e = cm::launch_prep(pb, stream)) != hipSuccess) return hip_fail(e, "sweep preparation");
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t i = idx[k];
-    cm_status st = enqueue_score(&ms[i], &ss[i], &rs[i], stream);
-    if (st != CM_OK) return st;
-  }
+  if ((e = cm::launch_score(sb, stream)) != hipSuccess) return hip_fail(e, "score kernel");
   return ok();
 }
 

@@ -24,6 +24,7 @@ struct SimArgs {
   double leak, comp;    // LCA
   uint32_t nonneg;
   uint32_t direct;  // 1: count finished runs straight into global memory
+  uint64_t trials_magic, steps_magic;  // udiv_magic multipliers for trials and max_steps
   const double* grid;
   const double* drive;     // LCA: [settings][9][2]
   const int32_t* correct;  // [stimuli]
@@ -34,6 +35,20 @@ struct SimArgs {
   uint8_t* run_flag;
   double* run_state;
 };
+
+// Quotient n / d of 32-bit values by one 64x32 multiply-high, with
+// M = floor((2^64 - 1) / d) + 1 (0 for d = 1).  Exact for every n < 2^32:
+// M = (2^64 + e) / d with 0 <= e <= d, so n M / 2^64 exceeds n / d by less
+// than 2^-32, less than the gap 1/d between n / d and the next integer.
+__host__ __device__ inline uint64_t udiv_magic_for(uint32_t d) {
+  return d == 1u ? 0ull : ~0ull / d + 1ull;
+}
+__host__ __device__ inline uint32_t udiv_magic(uint32_t n, uint64_t M) {
+  if (M == 0) return n;
+  const uint64_t lo = (uint64_t)n * (uint32_t)M;
+  const uint64_t hi = (uint64_t)n * (uint32_t)(M >> 32) + (lo >> 32);
+  return (uint32_t)(hi >> 32);
+}
 
 // Up to kMaxBatch sweeps of one kind and precision in one launch.
 constexpr uint32_t kMaxBatch = 12;
@@ -62,6 +77,30 @@ struct DriveArgs {
   const double* grid;
   double* drive;     // [settings][9][2]
   int32_t* correct;  // [9]
+};
+
+// Per-sweep preparation, many sweeps per launch: zero the histogram and
+// statistics, then write the correct-response table (and, for the conflict
+// network, the drive table).  Item k covers launch indices [end[k-1], end[k]).
+struct PrepItem {
+  uint64_t* hist;
+  uint64_t n_hist;
+  uint64_t* stats;
+  uint64_t n_stats;
+  uint32_t kind;  // CM_DDM: correct[0] = 1; CM_CONFLICT_LCA: drive and correct; else none
+  uint32_t pad;
+  DriveArgs d;  // d.correct for the DDM and the conflict network; the rest for the latter
+  uint64_t end;
+};
+struct PrepBatch {
+  uint32_t n;
+  uint32_t pad;
+  PrepItem it[kMaxBatch];
+};
+struct ScoreBatch {
+  uint32_t n;
+  uint32_t pad;
+  ScoreArgs a[kMaxBatch];
 };
 
 // Arguments of the rate-network kernels.
@@ -116,10 +155,8 @@ struct DensityArgs {
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
                            hipStream_t st);
-hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st);
-hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st);
-hipError_t launch_drive(const DriveArgs& a, hipStream_t st);
-hipError_t launch_score(const ScoreArgs& a, hipStream_t st);
+hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
+hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);
 hipError_t launch_rnn(int precision, const RnnArgs& a, uint32_t groups, hipStream_t st);
 hipError_t launch_uf_init(const UnfusedArgs& a, hipStream_t st);

@@ -1,5 +1,6 @@
-// prep.hip -- per-sweep preparation kernels: output zero-fill and the
-// conflict network's feed-forward drive.
+// prep.hip -- per-sweep preparation, all sweeps of a launch in one kernel:
+// output zero-fill, the correct-response table and the conflict network's
+// feed-forward drive.
 //
 // The drive of each accumulator depends only on (setting, stimulus), not on
 // the step, so it is evaluated once per pair instead of once per step: the
@@ -8,45 +9,36 @@
 // inputs -> two 4-unit logistic hidden layers whose gain the pathway's
 // control signal multiplies -> [2x4] projections summed onto the two
 // accumulators (logistic transfer and projections, Sec. 3.4.2).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace cm {
 namespace {
 
-__global__ void zero_u64_kernel(uint64_t* p, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0ull;
-}
-
-__global__ void fill_i32_kernel(int32_t* p, uint64_t n, int32_t v) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
 __device__ __forceinline__ double logistic(double v) { return 1.0 / (1.0 + exp(-v)); }
 
-// One thread per (setting, stimulus); block 0 also writes the correct
-// response per stimulus: the argmax of the relevant pathway (A) alone at
-// unit control, lowest index on ties.
-__global__ void drive_kernel(DriveArgs a) {
+// Correct response to stimulus `stim`: the argmax of the relevant pathway (A)
+// alone at unit control, lowest index on ties.
+__device__ void write_correct(const DriveArgs& a, int stim) {
+  const double* WA = a.weights;
+  const double* OA = a.weights + 24;
+  const int ia = stim / 3;
+  double sc[2];
+  for (int j = 0; j < 2; ++j) {
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k) acc = acc + OA[j * 4 + k] * logistic(a.gain * (WA[k * 3 + ia] + a.bias));
+    sc[j] = acc;
+  }
+  a.correct[stim] = sc[1] > sc[0] ? 1 : 0;
+}
+
+// Drive of both accumulators for entry i = 9 * setting + stimulus.
+__device__ void write_drive(const DriveArgs& a, uint64_t i) {
   const double* WA = a.weights;
   const double* WB = a.weights + 12;
   const double* OA = a.weights + 24;
   const double* OB = a.weights + 32;
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < 9) {
-    const int ia = threadIdx.x / 3;
-    double sc[2];
-    for (int j = 0; j < 2; ++j) {
-      double acc = 0.0;
-      for (int k = 0; k < 4; ++k) acc = acc + OA[j * 4 + k] * logistic(a.gain * (WA[k * 3 + ia] + a.bias));
-      sc[j] = acc;
-    }
-    a.correct[threadIdx.x] = sc[1] > sc[0] ? 1 : 0;
-  }
-  if (i >= a.n_settings * 9u) return;
   const uint64_t s = i / 9u;
   const int stim = (int)(i - s * 9u), ia = stim / 3, ib = stim % 3;
   const double cA = a.n_signals ? a.grid[s * a.n_signals] : 1.0;
@@ -64,30 +56,45 @@ __global__ void drive_kernel(DriveArgs a) {
   }
 }
 
-uint32_t grid_for(uint64_t n, uint32_t block) {
-  uint64_t g = (n + block - 1) / block;
-  if (g < 1) g = 1;
-  if (g > 65535) g = 65535;
-  return (uint32_t)g;
+// One thread per launch index.  An item's range is [hist | stats | tables]:
+// zero words first, then one index per correct-table entry (the DDM's one
+// entry, the conflict network's nine) and one per (setting, stimulus) drive.
+__global__ void prep_kernel(PrepBatch b) {
+  const uint64_t total = b.it[b.n - 1].end;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t k = 0;
+    while (i >= b.it[k].end) ++k;
+    const PrepItem& p = b.it[k];
+    uint64_t j = i - (k ? b.it[k - 1].end : 0);
+    if (j < p.n_hist) {
+      p.hist[j] = 0ull;
+      continue;
+    }
+    j -= p.n_hist;
+    if (j < p.n_stats) {
+      p.stats[j] = 0ull;
+      continue;
+    }
+    j -= p.n_stats;
+    if (p.kind == CM_DDM) {
+      p.d.correct[0] = 1;  // the upper boundary is the correct response
+    } else if (j < 9) {
+      write_correct(p.d, (int)j);
+    } else {
+      write_drive(p.d, j - 9);
+    }
+  }
 }
 
 }  // namespace
 
-hipError_t launch_zero_u64(uint64_t* p, uint64_t n, hipStream_t st) {
-  if (!n) return hipSuccess;
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_i32(int32_t* p, uint64_t n, int32_t v, hipStream_t st) {
-  if (!n) return hipSuccess;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_drive(const DriveArgs& a, hipStream_t st) {
-  const uint64_t n = a.n_settings * 9u;
-  hipLaunchKernelGGL(drive_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, a);
+hipError_t launch_prep(const PrepBatch& b, hipStream_t st) {
+  if (b.n < 1 || b.n > kMaxBatch) return hipErrorInvalidValue;
+  const uint64_t total = b.it[b.n - 1].end;
+  if (!total) return hipSuccess;
+  const uint64_t g = std::min<uint64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(prep_kernel, dim3((uint32_t)g), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 

@@ -19,7 +19,9 @@ namespace {
 
 constexpr int kScoreBlock = 1024;
 
-__global__ __launch_bounds__(kScoreBlock) void score_kernel(ScoreArgs a) {
+// One workgroup per sweep of the batch.
+__global__ __launch_bounds__(kScoreBlock) void score_kernel(ScoreBatch batch) {
+  const ScoreArgs& a = batch.a[blockIdx.x];
   __shared__ double red_d[kScoreBlock / 64];
   __shared__ unsigned long long red_k[kScoreBlock / 64];
   __shared__ unsigned long long red_c[kScoreBlock / 64];
@@ -85,8 +87,10 @@ __global__ __launch_bounds__(kScoreBlock) void score_kernel(ScoreArgs a) {
 
 }  // namespace
 
-hipError_t launch_score(const ScoreArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(score_kernel, dim3(1), dim3(kScoreBlock), 0, st, a);
+hipError_t launch_score(const ScoreBatch& b, hipStream_t st) {
+  if (b.n > kMaxBatch) return hipErrorInvalidValue;
+  if (!b.n) return hipSuccess;
+  hipLaunchKernelGGL(score_kernel, dim3(b.n), dim3(kScoreBlock), 0, st, b);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ __device__ __forceinline__ bool near_th(double q, double th, double eps) {
   return fabs(q - th) < eps;
 }
 
+
 // Record one finished run: LDS window (or global atomics in direct mode) and
 // optional per-run dumps.
 __device__ __forceinline__ void record(const SimArgs& a, uint32_t* lds, uint32_t s_lo,
@@ -46,7 +47,7 @@ __device__ __forceinline__ void record(const SimArgs& a, uint32_t* lds, uint32_t
   if (a.direct) {
     uint64_t* st = a.stats + (uint64_t)L.s * CM_NSTAT;
     if (c >= 0) {
-      const uint32_t bin = ((L.n - 1u) * a.n_bins) / a.max_steps;
+      const uint32_t bin = udiv_magic((L.n - 1u) * a.n_bins, a.steps_magic);
       atomicAdd((unsigned long long*)&a.hist[((uint64_t)L.s * 2u + c) * a.n_bins + bin], 1ull);
       atomicAdd((unsigned long long*)&st[CM_ST_DEC0 + c], 1ull);
       atomicAdd((unsigned long long*)&st[CM_ST_SUMN0 + c], (unsigned long long)n);
@@ -62,7 +63,7 @@ __device__ __forceinline__ void record(const SimArgs& a, uint32_t* lds, uint32_t
     uint32_t* cnt = rec + 2u * B;
     unsigned long long* sums = (unsigned long long*)(cnt + kCntWords);
     if (c >= 0) {
-      const uint32_t bin = ((L.n - 1u) * B) / a.max_steps;
+      const uint32_t bin = udiv_magic((L.n - 1u) * B, a.steps_magic);
       atomicAdd(&rec[c * B + bin], 1u);
       atomicAdd(&cnt[kCntDec0 + c], 1u);
       if (c == L.target) atomicAdd(&cnt[kCntCorrect], 1u);
@@ -137,15 +138,19 @@ struct DDM {
     L.target = 1;  // the upper boundary is the correct response
   }
 
+  // guard = thresh - 2 eps: nearer the origin no bound is within flag distance
   __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, double z, float zf, float af,
-                                      float bf) {
+                                      float bf, double guard) {
     if (PREC == CM_FP64) x = (x + a_step) + A.b * z;
     else x = x + (double)fmaf(bf, zf, af);
     L.n += 1;
-    const double th = A.thresh;
-    if (near_th(x, th, A.flag_eps) || near_th(x, -th, A.flag_eps)) L.flag = true;
-    if (x >= th) { L.choice = 1; return false; }
-    if (x <= -th) { L.choice = 0; return false; }
+    // one comparison per step; the exact tests run only within 2 eps of a bound
+    if (__builtin_expect(fabs(x) >= guard, 0)) {
+      const double th = A.thresh;
+      if (near_th(x, th, A.flag_eps) || near_th(x, -th, A.flag_eps)) L.flag = true;
+      if (x >= th) { L.choice = 1; return false; }
+      if (x <= -th) { L.choice = 0; return false; }
+    }
     if (L.n == A.max_steps) { L.choice = -1; return false; }
     return true;
   }
@@ -153,14 +158,15 @@ struct DDM {
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int pairs) {
     const float af = (float)a_step, bf = (float)A.b;
+    const double guard = A.thresh - 2.0 * A.flag_eps;
     for (int p = 0; p < pairs; ++p) {
       const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
       double z0 = 0, z1 = 0;
       float f0 = 0, f1 = 0;
       if (PREC == CM_FP64) normals64(w, z0, z1);
       else normals32(w, f0, f1);
-      if (!one(A, L, z0, f0, af, bf)) return false;
-      if (!one(A, L, z1, f1, af, bf)) return false;
+      if (!one(A, L, z0, f0, af, bf, guard)) return false;
+      if (!one(A, L, z1, f1, af, bf, guard)) return false;
     }
     return true;
   }
@@ -187,7 +193,7 @@ struct LCA {
 
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int steps) {
-    const double th = A.thresh, eps = A.flag_eps;
+    const double th = A.thresh, eps = A.flag_eps, guard = th - 2.0 * eps;
     for (int k = 0; k < steps; ++k) {
       const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
       double y0, y1;
@@ -213,12 +219,16 @@ struct LCA {
       x0 = y0;
       x1 = y1;
       L.n += 1;
-      if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+      // one comparison per step; the exact tests run only within 2 eps of
+      // the threshold, where a unit can be within flag distance or across
       const double mx = x0 > x1 ? x0 : x1;
-      if (mx >= th) {
-        L.choice = (x1 > x0) ? 1 : 0;
-        if (fabs(x0 - x1) < eps) L.flag = true;
-        return false;
+      if (__builtin_expect(mx >= guard, 0)) {
+        if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+        if (mx >= th) {
+          L.choice = (x1 > x0) ? 1 : 0;
+          if (fabs(x0 - x1) < eps) L.flag = true;
+          return false;
+        }
       }
       if (L.n == A.max_steps) { L.choice = -1; return false; }
     }
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   bool have = off < len;
   auto setup = [&](uint32_t o) {
     const uint32_t local = t_lo + o;  // < 2^31 + chunk
-    L.s = s_lo + local / T;
+    L.s = s_lo + udiv_magic(local, a.trials_magic);
     L.t = local - (L.s - s_lo) * T;
     L.n = 0;
     L.choice = -1;
@@ -329,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
   for (uint32_t off = wave; off < len; off += nwave) {
     Lane L;
     const uint32_t local = t_lo + off;
-    L.s = s_lo + local / T;
+    L.s = s_lo + udiv_magic(local, a.trials_magic);
     L.t = local - (L.s - s_lo) * T;
     L.target = 1;
     L.flag = false;
