@@ -74,6 +74,11 @@ def lib():
                                                           C.POINTER(C.c_double),
                                                           C.POINTER(C.c_double)]
         L.cmo_ddm_density.restype = C.c_int
+        L.cmo_timecourse.argtypes = [C.POINTER(_Model), C.POINTER(_Sweep), C.c_uint32,
+                                     C.POINTER(C.c_int64), C.c_int]
+        L.cmo_timecourse.restype = C.c_int
+        L.cmo_tc_quant.argtypes = [C.c_double]
+        L.cmo_tc_quant.restype = C.c_int64
         L.cmo_state_width.argtypes = [C.POINTER(_Model)]
         L.cmo_state_width.restype = C.c_int
         _lib = L
@@ -148,6 +153,38 @@ def trajectory(w, setting, trial):
     if n == 0:
         raise ValueError("oracle rejected the trajectory request")
     return buf[:n].copy(), int(ch.value), int(fl.value)
+
+
+TC_WORDS = 6
+TC = dict(count=0, x0=1, x1=2, x0sq=3, x1sq=4, energy=5)
+TC_SCALE = 2.0 ** 32
+
+
+def timecourse(w, every, n_threads=0):
+    """Ensemble time course [settings, K = max_steps // every, 6] int64 (see
+    cmo_timecourse: count, then fixed-point sums of x0, x1, x0^2, x1^2 and the
+    conflict energy comp*x0*x1 over the runs that executed each sample step)."""
+    m, s, keep = _structs(w)
+    S, K = int(w["n_settings"]), int(w["max_steps"]) // int(every)
+    tc = np.zeros((S, K, TC_WORDS), np.int64)
+    rc = lib().cmo_timecourse(C.byref(m), C.byref(s), int(every), _ptr(tc, C.c_int64),
+                              int(n_threads))
+    if rc:
+        raise ValueError(f"oracle rejected the time-course request (code {rc})")
+    return tc
+
+
+def tc_quant(v):
+    return int(lib().cmo_tc_quant(float(v)))
+
+
+def tc_moments(tc, scale=TC_SCALE):
+    """Per (setting, sample): count and the means of x0, x1, x0^2, x1^2 and
+    the energy over contributing runs (NaN where no run contributes)."""
+    cnt = tc[..., 0].astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        means = tc[..., 1:].astype(np.float64) / scale / cnt[..., None]
+    return cnt, means
 
 
 def philox(ctr, key):

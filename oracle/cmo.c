@@ -501,6 +501,65 @@ uint32_t cmo_trajectory(const cmo_model *m, const cmo_sweep *s, int64_t setting,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Time course: ensemble statistics of the state at sample steps, the         */
+/* dynamics over time that modellers study beside final outcomes (Sec. 1,     */
+/* Sec. 2.1), including the conflict energy of the two mutually inhibiting    */
+/* response units (the Stroop model's decision energy, Sec. 4.4).  Sums are   */
+/* integers of fixed-point values, so they do not depend on summation order.  */
+/* ------------------------------------------------------------------------ */
+int64_t cmo_tc_quant(double v) {
+  const double lim = 4611686018427387904.0; /* 2^62 */
+  double t = nearbyint(ldexp(v, 32));
+  if (t > lim) t = lim;
+  if (t < -lim) t = -lim;
+  return (int64_t)t;
+}
+
+static void tc_add(int64_t *w, double x0, double x1, double comp) {
+  uint64_t *u = (uint64_t *)w; /* wrap-around sums */
+  u[0] += 1u;
+  u[1] += (uint64_t)cmo_tc_quant(x0);
+  u[2] += (uint64_t)cmo_tc_quant(x1);
+  u[3] += (uint64_t)cmo_tc_quant(x0 * x0);
+  u[4] += (uint64_t)cmo_tc_quant(x1 * x1);
+  u[5] += (uint64_t)cmo_tc_quant(comp * (x0 * x1));
+}
+
+int cmo_timecourse(const cmo_model *m, const cmo_sweep *s, uint32_t every, int64_t *tc,
+                   int n_threads) {
+  if (invalid(m, s) || !tc || every < 1 || every > s->max_steps) return 1;
+  if (m->kind != CMO_DDM && m->kind != CMO_LCA) return 1;
+  const int64_t S = s->n_settings;
+  const uint64_t T = s->trials;
+  const uint32_t K = s->max_steps / every, N = s->max_steps;
+  const int width = cmo_state_width(m);
+  const double comp = m->kind == CMO_LCA ? param(m, CMO_LCA_COMP) : 0.0;
+  memset(tc, 0, sizeof(int64_t) * (size_t)S * K * CMO_TC_WORDS);
+  int fail = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t setting = 0; setting < S; ++setting) {
+    double *traj = malloc(sizeof(double) * (size_t)N * width);
+    if (!traj) {
+      fail = 1;
+      continue;
+    }
+    int64_t *row = tc + (size_t)setting * K * CMO_TC_WORDS;
+    for (uint64_t trial = 0; trial < T; ++trial) {
+      run_out o = run_one(m, s, NULL, setting, trial, NULL, traj);
+      for (uint32_t k = 1; k <= K && (uint64_t)k * every <= o.steps; ++k) {
+        const double *x = traj + (size_t)(k * every - 1) * width;
+        tc_add(row + (size_t)(k - 1) * CMO_TC_WORDS, x[0], width > 1 ? x[1] : 0.0, comp);
+      }
+    }
+    free(traj);
+  }
+  return fail ? 2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* First-passage distribution of the discretised DDM by propagating the      */
 /* survivor mass on M cells of (-theta, theta): the walk's transition from   */
 /* a point is Gaussian, so the mass a cell receives is a difference of       */

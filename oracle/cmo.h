@@ -102,6 +102,22 @@ uint32_t cmo_trajectory(const cmo_model *m, const cmo_sweep *s, int64_t setting,
  * once the survivor mass falls below tol (remaining entries 0). */
 int cmo_ddm_density(double a, double b, double theta, double start, int cells, int max_steps,
                     double tol, double *lower, double *upper);
+/* Time course of the ensemble: at every sample step n = every*k (k = 1..K,
+ * K = max_steps / every) the runs of each setting that executed step n (their
+ * decision step is n or later) contribute their state after step n.
+ * tc[(setting*K + k-1)*CMO_TC_WORDS + c] receives, for c =
+ *   0 count of contributing runs,
+ *   1 sum q(x0), 2 sum q(x1), 3 sum q(x0*x0), 4 sum q(x1*x1),
+ *   5 sum q(comp*(x0*x1)) (the response layer's conflict energy),
+ * with q(v) = v*2^32 rounded to nearest (ties to even), clamped to +-2^62,
+ * and two's-complement (mod 2^64) sums.  The DDM has x1 = 0 (words 2, 4 and
+ * 5 stay 0).  DDM and conflict LCA only.  Returns 0 on success. */
+#define CMO_TC_WORDS 6
+int cmo_timecourse(const cmo_model *m, const cmo_sweep *s, uint32_t every, int64_t *tc,
+                   int n_threads);
+/* the quantisation above, for pins */
+int64_t cmo_tc_quant(double v);
+
 /* round-to-nearest-even double -> float -> bfloat16 bits */
 uint16_t cmo_bf16_bits(double v);
 int cmo_state_width(const cmo_model *m);
