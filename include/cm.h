@@ -203,6 +203,23 @@ cm_status cm_launch_batch(cm_handle *h, uint32_t n, const cm_model *models,
                           void *const *workspaces, const uint64_t *workspace_bytes,
                           void *hip_stream);
 
+/* Time course: what cm_launch computes, plus ensemble statistics of the state
+ * over time -- the dynamics modellers study beside final outcomes (Distill,
+ * Sec. 1 and 2.1), including the conflict energy of the two mutually
+ * inhibiting response units that the Stroop model tracks (Sec. 4.4).  At
+ * every sample step n = every*k, k = 1..K with K = max_steps / every, the runs
+ * of a setting whose decision step is n or later contribute their state after
+ * step n.  timecourse (DEVICE, 8-byte aligned, [n_settings][K][6] int64,
+ * zero-filled by the call) receives per (setting, k): the count of
+ * contributing runs, then the sums of q(x0), q(x1), q(x0*x0), q(x1*x1) and
+ * q(comp*(x0*x1)) with q(v) = v*2^32 rounded to nearest even and clamped to
+ * +-2^62, summed modulo 2^64 (integer sums: independent of run order and
+ * launch shape).  The DDM has one unit (x1 = 0).  Kinds CM_DDM and
+ * CM_CONFLICT_LCA, precisions FP64 and FP32_STEP; 1 <= every <= max_steps. */
+cm_status cm_launch_timecourse(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
+                               const cm_result *result, uint32_t every, int64_t *timecourse,
+                               void *workspace, uint64_t workspace_bytes, void *hip_stream);
+
 /* Ablation: the same sweep executed node by node, the GPU analogue of the
  * Distill paper's per-node compilation (Sec. 6.2): each step runs as separate
  * kernels for the random numbers, the accumulator update and the threshold
@@ -231,6 +248,45 @@ cm_status cm_launch_unfused(cm_handle *h, const cm_model *model, const cm_sweep 
  * precision are not used. */
 cm_status cm_ddm_density(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
                          uint32_t n_cells, double tol, double *first_passage, void *hip_stream);
+
+/* Serving queue: asynchronous submission of batches on the handle's own
+ * streams ("slots"), for a server that admits simulation requests while
+ * others are still on the GPU.  Runs are independent and keyed by their own
+ * (seed, setting, trial, step), so a request computes the same outputs
+ * whatever else is in flight (Sec. 3.6).
+ *
+ * cm_serve_config creates n_slots streams (1..64, default priority) and an
+ * event per slot; it fails with CM_E_BUSY while a slot holds unfinished work.
+ * The first cm_submit on a handle creates 4 slots if none exist.
+ *
+ * cm_submit enqueues cm_launch_batch of entries 0..n-1 on a free slot and, when
+ * host is not NULL, copies of each entry's hist, stats, score and best into
+ * host[i]'s buffers (NULL fields skipped; sizes as in cm_result).  Host
+ * buffers should be pinned (hipHostMalloc) for the copies to be
+ * asynchronous.  producer_stream (a hipStream_t or NULL for none) is the
+ * stream that wrote the inputs: the slot first waits for all work enqueued
+ * on it so far.  *ticket receives a positive ticket.  CM_E_BUSY: every slot
+ * holds unfinished work (nothing was enqueued; retry after cm_poll reports a
+ * completion).  Other errors are those of cm_launch_batch; nothing is then
+ * enqueued.  Device buffers and host buffers must stay alive until cm_poll
+ * reports the ticket done.
+ *
+ * cm_poll sets *done to 1 once all work of the ticket, copies included, has
+ * finished (the host buffers then hold the results), else to 0; it never
+ * waits.  Unknown tickets (0 or not yet issued) give CM_E_INVALID.
+ * A handle's queue is not thread-safe: submit and poll from one thread. */
+typedef struct {
+  uint64_t *hist;  /* HOST [n_settings][2][n_bins] or NULL */
+  uint64_t *stats; /* HOST [n_settings][CM_NSTAT] or NULL */
+  double *score;   /* HOST [n_settings] or NULL */
+  int64_t *best;   /* HOST [2] or NULL */
+} cm_host_result;
+cm_status cm_serve_config(cm_handle *h, uint32_t n_slots);
+cm_status cm_submit(cm_handle *h, uint32_t n, const cm_model *models, const cm_sweep *sweeps,
+                    const cm_result *results, void *const *workspaces,
+                    const uint64_t *workspace_bytes, const cm_host_result *host,
+                    void *producer_stream, uint64_t *ticket);
+cm_status cm_poll(cm_handle *h, uint64_t ticket, int *done);
 
 /* Kernel timing.  While enabled, every cm_launch brackets its simulation
  * kernel with a pair of HIP events on the launch stream.  cm_profile_read

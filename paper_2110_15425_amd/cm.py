@@ -19,12 +19,16 @@ OK, E_INVALID, E_BUDGET, E_DEVICE, E_UNSUPPORTED, E_BUSY = range(6)
 STATUS_NAMES = {0: "CM_OK", 1: "CM_E_INVALID", 2: "CM_E_BUDGET", 3: "CM_E_DEVICE",
                 4: "CM_E_UNSUPPORTED", 5: "CM_E_BUSY"}
 NSTAT = 9
+TC_WORDS = 6  # time course per sample: count, sums of x0, x1, x0^2, x1^2, energy
+TC_SCALE = 2.0 ** 32
 ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1=7, flagged=8)
 
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
-           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_unfused_workspace_bytes",
-           "cm_launch_unfused", "cm_ddm_density", "cm_profile", "cm_profile_read", "cm_last_error"]
+           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_launch_timecourse",
+           "cm_unfused_workspace_bytes",
+           "cm_launch_unfused", "cm_ddm_density", "cm_serve_config", "cm_submit", "cm_poll",
+           "cm_profile", "cm_profile_read", "cm_last_error"]
 
 
 class CmError(RuntimeError):
@@ -58,6 +62,11 @@ class Tuning(C.Structure):
                 ("lanes_per_run", C.c_uint32)]
 
 
+class HostResult(C.Structure):
+    _fields_ = [("hist", C.c_void_p), ("stats", C.c_void_p), ("score", C.c_void_p),
+                ("best", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -80,10 +89,18 @@ def lib():
         L.cm_launch_batch.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
                                       C.POINTER(Result), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_uint64), C.c_void_p]
+        L.cm_launch_timecourse.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep),
+                                           C.POINTER(Result), C.c_uint32, C.c_void_p, C.c_void_p,
+                                           C.c_uint64, C.c_void_p]
         L.cm_unfused_workspace_bytes.argtypes = L.cm_workspace_bytes.argtypes
         L.cm_launch_unfused.argtypes = L.cm_launch.argtypes
         L.cm_ddm_density.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.c_uint32,
                                      C.c_double, C.c_void_p, C.c_void_p]
+        L.cm_serve_config.argtypes = [C.c_void_p, C.c_uint32]
+        L.cm_submit.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
+                                C.POINTER(Result), C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
+                                C.POINTER(HostResult), C.c_void_p, C.POINTER(C.c_uint64)]
+        L.cm_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
         L.cm_profile.argtypes = [C.c_void_p, C.c_int]
         L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.cm_last_error.restype = C.c_char_p
@@ -232,6 +249,20 @@ class DeviceSweep:
                                       C.byref(self.result), C.c_void_p(self.uf_workspace.data_ptr()),
                                       self.uf_workspace.numel(), C.c_void_p(st.cuda_stream)))
 
+    def launch_timecourse(self, every, stream=None):
+        """cm_launch_timecourse: the sweep plus its ensemble time course, kept
+        in ``self.timecourse`` ([settings, max_steps // every, 6] int64)."""
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
+        K = int(self.w["max_steps"]) // max(1, int(every))
+        self.timecourse = torch.empty((int(self.w["n_settings"]), K, TC_WORDS), dtype=torch.int64,
+                                      device=self.workspace.device)
+        check(lib().cm_launch_timecourse(self.handle.h, C.byref(self.model), C.byref(self.sweep),
+                                         C.byref(self.result), int(every),
+                                         C.c_void_p(self.timecourse.data_ptr()),
+                                         C.c_void_p(self.workspace.data_ptr()),
+                                         self.workspace.numel(), C.c_void_p(st.cuda_stream)))
+
     def launch(self, stream=None):
         torch = self.torch
         st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
@@ -264,6 +295,54 @@ def launch_batch(handle, sweeps, stream=None):
     wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
     wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
     check(lib().cm_launch_batch(handle.h, n, models, sws, res, wsp, wsb, C.c_void_p(st.cuda_stream)))
+
+
+def serve_config(handle, n_slots):
+    """Give the handle n_slots serving streams (cm_serve_config)."""
+    check(lib().cm_serve_config(handle.h, int(n_slots)))
+
+
+def host_buffers(d):
+    """Pinned host tensors matching a DeviceSweep's hist, stats, score and best."""
+    import torch
+    return {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
+            for k, v in (("hist", d.hist), ("stats", d.stats), ("score", d.score),
+                         ("best", d.best)) if v is not None}
+
+
+def submit(handle, sweeps, host=None, producer=None):
+    """Enqueue DeviceSweeps on a free serving slot of the handle (cm_submit);
+    ``host`` is a list of dicts of pinned tensors (see host_buffers) that
+    receive the results.  ``producer`` is the torch stream that wrote the
+    inputs (default: the current stream).  Returns the ticket, or None when
+    every slot is busy."""
+    import torch
+    n = len(sweeps)
+    prod = producer if producer is not None else torch.cuda.current_stream(handle.device)
+    models = (Model * n)(*[d.model for d in sweeps])
+    sws = (Sweep * n)(*[d.sweep for d in sweeps])
+    res = (Result * n)(*[d.result for d in sweeps])
+    wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
+    wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
+    hr = None
+    if host is not None:
+        ptr = lambda hh, k: hh[k].data_ptr() if k in hh else None  # noqa: E731
+        hr = (HostResult * n)(*[HostResult(ptr(hh, "hist"), ptr(hh, "stats"), ptr(hh, "score"),
+                                           ptr(hh, "best")) for hh in host])
+    t = C.c_uint64(0)
+    st = lib().cm_submit(handle.h, n, models, sws, res, wsp, wsb, hr,
+                         C.c_void_p(prod.cuda_stream), C.byref(t))
+    if st == E_BUSY:
+        return None
+    check(st)
+    return int(t.value)
+
+
+def poll(handle, ticket):
+    """True once all work of the ticket (result copies included) has finished."""
+    d = C.c_int(0)
+    check(lib().cm_poll(handle.h, int(ticket), C.byref(d)))
+    return bool(d.value)
 
 
 def ddm_density(w, cells=1000, tol=1e-15, handle=None):
@@ -301,6 +380,15 @@ def run(w, dumps=False, handle=None):
     ds = DeviceSweep(handle or default_handle(), w, dumps=dumps)
     ds.launch()
     return ds.results()
+
+
+def timecourse(w, every, handle=None):
+    """Run one sweep with its time course on the GPU: (outputs as in run(),
+    timecourse [settings, max_steps // every, 6] int64)."""
+    ds = DeviceSweep(handle or default_handle(), w)
+    ds.launch_timecourse(every)
+    out = ds.results()
+    return out, ds.timecourse.cpu().numpy()
 
 
 def run_steps(w, out):

@@ -27,6 +27,15 @@ struct cm_handle {
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t used = 0;
+  // serving queue: one stream, completion event and input hand-off event per slot
+  struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr, handoff = nullptr;
+    uint64_t ticket = 0;
+    bool busy = false;
+  };
+  std::vector<Slot> slots;
+  uint64_t next_ticket = 1;
 };
 
 namespace {
@@ -213,6 +222,44 @@ cm_status hip_fail(hipError_t e, const char* what) {
   return fail(CM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Serving slots.  A busy slot becomes free once its completion event has fired.
+cm_status refresh_slot(cm_handle::Slot& sl) {
+  if (!sl.busy) return CM_OK;
+  const hipError_t e = hipEventQuery(sl.done);
+  if (e == hipSuccess) {
+    sl.busy = false;
+    return CM_OK;
+  }
+  if (e == hipErrorNotReady) return CM_OK;
+  return hip_fail(e, "hipEventQuery");
+}
+
+void release_slots(cm_handle* h) {
+  for (auto& sl : h->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.handoff) (void)hipEventDestroy(sl.handoff);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  h->slots.clear();
+}
+
+cm_status make_slots(cm_handle* h, uint32_t n) {
+  release_slots(h);
+  h->slots.resize(n);
+  for (auto& sl : h->slots) {
+    hipError_t e;
+    // default priority (no priority argument), non-blocking w.r.t. the null stream
+    if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.handoff, hipEventDisableTiming)) != hipSuccess) {
+      release_slots(h);
+      return hip_fail(e, "serving slot");
+    }
+  }
+  return CM_OK;
+}
+
 // Events around the simulation kernel when profiling is on.
 struct ProfScope {
   cm_handle* h;
@@ -260,9 +307,16 @@ bool scan_ddm(const cm_tuning& t, uint64_t runs) {
 // Kernel arguments and launch shape of one lane-kernel sweep.
 // launch_runs: runs of every sweep in the same launch (sets the automatic
 // runs per lane, which trades GPU fill against the tail of each chunk).
+// Time course requested with a launch: output [settings][K][6] and the
+// sample spacing (every = 0: none).
+struct TcSpec {
+  int64_t* out = nullptr;
+  uint32_t every = 0;
+};
+
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
-                    const Layout& L, bool scan, uint64_t launch_runs, cm::SimArgs& a,
-                    uint64_t& groups, size_t& lds) {
+                    const Layout& L, bool scan, uint64_t launch_runs, const TcSpec& tc,
+                    cm::SimArgs& a, uint64_t& groups, size_t& lds) {
   const cm_tuning& tune = h->tune[m->kind][m->precision];
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
@@ -317,7 +371,12 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     chunk = (uint64_t)tune.block * rpl;
   }
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
-  const size_t rec_bytes = 4u * cm::rec_words(B);
+  if (tc.every) {
+    a.tc = tc.out;
+    a.tc_every = tc.every;
+    a.tc_k = s->max_steps / tc.every;
+  }
+  const size_t rec_bytes = 4u * (cm::rec_words(B) + (tc.every ? cm::tc_words(a.tc_k) : 0u));
   const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
   bool direct = false;
   // settings touched by one chunk: at most floor((chunk-1)/T) + 2
@@ -337,7 +396,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
 // Output zero-fill and the per-sweep tables the simulation reads.
 // Preparation of one sweep as item k of a batched prep launch.
 void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws, const Layout& L,
-               cm::PrepBatch& b) {
+               cm::PrepBatch& b, const TcSpec& tc = TcSpec{}) {
   cm::PrepItem& it = b.it[b.n];
   const uint64_t S = s->n_settings;
   const double* p = m->params;
@@ -347,6 +406,10 @@ void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* w
   it.stats = r->stats;
   it.n_stats = S * CM_NSTAT;
   it.kind = (uint32_t)m->kind;
+  if (tc.every) {
+    it.extra = (uint64_t*)tc.out;
+    it.n_extra = S * (uint64_t)(s->max_steps / tc.every) * cm::kTcWords;
+  }
   uint64_t tables = 0;
   if (m->kind == CM_DDM) {
     it.d.correct = (int32_t*)(ws + L.correct);
@@ -363,7 +426,7 @@ void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* w
     it.d.correct = (int32_t*)(ws + L.correct);
     tables = 9 + S * 9u;
   }
-  it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + tables;
+  it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + it.n_extra + tables;
   ++b.n;
 }
 
@@ -446,9 +509,10 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
 // One launch of the lane kernel over the sweeps idx[0..n) (same kind and precision).
 cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm_model* ms, const cm_sweep* ss,
                             const cm_result* rs, void* const* wss, const Layout* Ls, const uint32_t* idx,
-                            uint32_t n, hipStream_t stream) {
-  // one form per launch: the DDM scan form when every sweep of the group is small
-  bool scan = kind == CM_DDM;
+                            uint32_t n, hipStream_t stream, const TcSpec& tc = TcSpec{}) {
+  // one form per launch: the DDM scan form when every sweep of the group is
+  // small (the time course needs the lane form)
+  bool scan = kind == CM_DDM && !tc.every;
   for (uint32_t k = 0; k < n && scan; ++k) {
     const uint32_t i = idx[k];
     scan = scan_ddm(h->tune[kind][prec], ss[i].n_settings * ss[i].trials);
@@ -464,7 +528,7 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     uint64_t groups = 0;
     size_t l = 0;
     cm_status st =
-        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, launch_runs, b.a[k], groups, l);
+        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, launch_runs, tc, b.a[k], groups, l);
     if (st != CM_OK) return st;
     b.base[k] = base;
     base += groups;
@@ -476,14 +540,14 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   cm::ScoreBatch sb{};
   for (uint32_t k = 0; k < n; ++k) {
     const uint32_t i = idx[k];
-    fill_prep(&ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], pb);
+    fill_prep(&ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], pb, tc);
     fill_score(&ms[i], &ss[i], &rs[i], sb);
   }
   hipError_t e;
   if ((e = cm::launch_prep(pb, stream)) != hipSuccess) return hip_fail(e, "sweep preparation");
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, b, lds, stream)) != hipSuccess)
+  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, tc.every != 0, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_score(sb, stream)) != hipSuccess) return hip_fail(e, "score kernel");
@@ -531,6 +595,10 @@ cm_status cm_create(int device_ordinal, cm_handle** out) {
 }
 
 cm_status cm_destroy(cm_handle* h) {
+  if (h) {
+    DeviceGuard guard(h->device);
+    release_slots(h);
+  }
   if (h && h->host_count) (void)hipHostFree(h->host_count);
   if (h) {
     for (auto& ev : h->events) {
@@ -539,6 +607,96 @@ cm_status cm_destroy(cm_handle* h) {
     }
   }
   delete h;
+  return ok();
+}
+
+cm_status cm_serve_config(cm_handle* h, uint32_t n_slots) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  if (n_slots < 1 || n_slots > 64) return fail(CM_E_INVALID, "n_slots must be in [1, 64]");
+  DeviceGuard guard(h->device);
+  for (auto& sl : h->slots) {
+    cm_status st = refresh_slot(sl);
+    if (st != CM_OK) return st;
+    if (sl.busy) return fail(CM_E_BUSY, "a slot still holds unfinished work");
+  }
+  return make_slots(h, n_slots);
+}
+
+cm_status cm_submit(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
+                    const cm_result* results, void* const* workspaces, const uint64_t* workspace_bytes,
+                    const cm_host_result* host, void* producer_stream, uint64_t* ticket) {
+  if (!h || !ticket) return fail(CM_E_INVALID, "handle and ticket must not be NULL");
+  if (n < 1 || !models || !sweeps || !results || !workspaces || !workspace_bytes)
+    return fail(CM_E_INVALID, "batch needs n >= 1 and non-NULL arrays");
+  // validate everything before touching a slot: no partial enqueue
+  for (uint32_t i = 0; i < n; ++i) {
+    Layout L;
+    cm_status st = check_launch(&models[i], &sweeps[i], &results[i], workspaces[i], workspace_bytes[i], L);
+    if (st != CM_OK) {
+      if (n > 1) g_err = "batch entry " + std::to_string(i) + ": " + g_err;
+      return st;
+    }
+  }
+  DeviceGuard guard(h->device);
+  if (h->slots.empty()) {
+    cm_status st = make_slots(h, 4);
+    if (st != CM_OK) return st;
+  }
+  cm_handle::Slot* slot = nullptr;
+  for (auto& sl : h->slots) {
+    cm_status st = refresh_slot(sl);
+    if (st != CM_OK) return st;
+    if (!sl.busy) {
+      slot = &sl;
+      break;
+    }
+  }
+  if (!slot) return fail(CM_E_BUSY, "all %zu slots hold unfinished work", h->slots.size());
+  hipError_t e;
+  if (producer_stream) {
+    if ((e = hipEventRecord(slot->handoff, (hipStream_t)producer_stream)) != hipSuccess)
+      return hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(slot->stream, slot->handoff, 0)) != hipSuccess)
+      return hip_fail(e, "hipStreamWaitEvent");
+  }
+  cm_status st = cm_launch_batch(h, n, models, sweeps, results, workspaces, workspace_bytes, slot->stream);
+  if (st != CM_OK) return st;
+  if (host) {
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint64_t S = sweeps[i].n_settings;
+      const struct {
+        void* dst;
+        const void* src;
+        uint64_t bytes;
+      } cp[4] = {{host[i].hist, results[i].hist, S * 2u * sweeps[i].n_bins * 8u},
+                 {host[i].stats, results[i].stats, S * CM_NSTAT * 8u},
+                 {host[i].score, results[i].score, S * 8u},
+                 {host[i].best, results[i].best, 16u}};
+      for (const auto& c : cp) {
+        if (!c.dst || !c.src) continue;
+        if ((e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost, slot->stream)) != hipSuccess)
+          return hip_fail(e, "result copy");
+      }
+    }
+  }
+  if ((e = hipEventRecord(slot->done, slot->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  slot->ticket = h->next_ticket++;
+  slot->busy = true;
+  *ticket = slot->ticket;
+  return ok();
+}
+
+cm_status cm_poll(cm_handle* h, uint64_t ticket, int* done) {
+  if (!h || !done) return fail(CM_E_INVALID, "handle and done must not be NULL");
+  if (ticket == 0 || ticket >= h->next_ticket) return fail(CM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  DeviceGuard guard(h->device);
+  *done = 1;  // a ticket no slot holds any more has finished (slots are reused only when done)
+  for (auto& sl : h->slots) {
+    if (sl.ticket != ticket) continue;
+    cm_status st = refresh_slot(sl);
+    if (st != CM_OK) return st;
+    *done = sl.busy ? 0 : 1;
+  }
   return ok();
 }
 
@@ -592,6 +750,26 @@ cm_status cm_get_tuning(cm_handle* h, uint32_t kind, uint32_t precision, cm_tuni
 cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
                     void* workspace, uint64_t workspace_bytes, void* hip_stream) {
   return cm_launch_batch(h, 1, m, s, r, &workspace, &workspace_bytes, hip_stream);
+}
+
+cm_status cm_launch_timecourse(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                               uint32_t every, int64_t* timecourse, void* workspace,
+                               uint64_t workspace_bytes, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  Layout L;
+  cm_status st = check_launch(m, s, r, workspace, workspace_bytes, L);
+  if (st != CM_OK) return st;
+  if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "the time course covers the DDM and the conflict LCA");
+  if (every < 1 || every > s->max_steps) return fail(CM_E_INVALID, "every must be in [1, max_steps]");
+  if (!timecourse || !aligned(timecourse, 8)) return fail(CM_E_INVALID, "timecourse must be non-NULL and 8-byte aligned");
+  DeviceGuard guard(h->device);
+  const uint32_t idx = 0;
+  TcSpec tc;
+  tc.out = timecourse;
+  tc.every = every;
+  return launch_lane_group(h, (uint32_t)m->kind, (uint32_t)m->precision, m, s, r, &workspace, &L, &idx, 1,
+                           (hipStream_t)hip_stream, tc);
 }
 
 cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,

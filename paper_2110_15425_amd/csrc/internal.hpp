@@ -13,6 +13,10 @@ namespace cm {
 // then 4 uint64 sums (sum n for choice 0/1, sum n^2 for choice 0/1).
 enum { kCntDec0 = 0, kCntDec1, kCntUndec, kCntCorrect, kCntFlagged, kCntWords = 8 };
 __host__ __device__ inline uint32_t rec_words(uint32_t n_bins) { return 2u * n_bins + kCntWords + 8u; }
+// Time-course block per setting: K samples x kTcWords 64-bit sums (count,
+// x0, x1, x0^2, x1^2, energy), in 32-bit words.
+constexpr uint32_t kTcWords = 6;
+__host__ __device__ inline uint32_t tc_words(uint32_t k) { return 2u * kTcWords * k; }
 
 // Arguments of the lane-per-run simulation kernels (DDM, conflict LCA).
 struct SimArgs {
@@ -25,6 +29,8 @@ struct SimArgs {
   uint32_t nonneg;
   uint32_t direct;  // 1: count finished runs straight into global memory
   uint64_t trials_magic, steps_magic;  // udiv_magic multipliers for trials and max_steps
+  int64_t* tc;                         // time course [n_settings][tc_k][kTcWords] or NULL
+  uint32_t tc_every, tc_k;
   const double* grid;
   const double* drive;     // LCA: [settings][9][2]
   const int32_t* correct;  // [stimuli]
@@ -80,13 +86,15 @@ struct DriveArgs {
 };
 
 // Per-sweep preparation, many sweeps per launch: zero the histogram and
-// statistics, then write the correct-response table (and, for the conflict
-// network, the drive table).  Item k covers launch indices [end[k-1], end[k]).
+// statistics (and the time course), then write the correct-response table
+// (and, for the conflict network, the drive table).  Item k covers launch indices [end[k-1], end[k]).
 struct PrepItem {
   uint64_t* hist;
   uint64_t n_hist;
   uint64_t* stats;
   uint64_t n_stats;
+  uint64_t* extra;  // a third range to zero (the time course) or NULL
+  uint64_t n_extra;
   uint32_t kind;  // CM_DDM: correct[0] = 1; CM_CONFLICT_LCA: drive and correct; else none
   uint32_t pad;
   DriveArgs d;  // d.correct for the DDM and the conflict network; the rest for the latter
@@ -153,8 +161,8 @@ struct DensityArgs {
 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
-                           hipStream_t st);
+hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const LaneBatch& b,
+                           size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);

@@ -56,7 +56,7 @@ __device__ void write_drive(const DriveArgs& a, uint64_t i) {
   }
 }
 
-// One thread per launch index.  An item's range is [hist | stats | tables]:
+// One thread per launch index.  An item's range is [hist | stats | extra | tables]:
 // zero words first, then one index per correct-table entry (the DDM's one
 // entry, the conflict network's nine) and one per (setting, stimulus) drive.
 __global__ void prep_kernel(PrepBatch b) {
@@ -77,6 +77,11 @@ __global__ void prep_kernel(PrepBatch b) {
       continue;
     }
     j -= p.n_stats;
+    if (j < p.n_extra) {
+      p.extra[j] = 0ull;
+      continue;
+    }
+    j -= p.n_extra;
     if (p.kind == CM_DDM) {
       p.d.correct[0] = 1;  // the upper boundary is the correct response
     } else if (j < 9) {

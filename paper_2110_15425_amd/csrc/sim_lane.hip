@@ -17,6 +17,8 @@
 // histogram covering the few settings the chunk spans and flushed with one
 // global 64-bit atomic per nonzero bin when the chunk is done.  All
 // reductions are integer additions: results do not depend on the schedule.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "rng.hpp"
 
@@ -31,6 +33,49 @@ struct Lane {
   int32_t target;  // correct response for this trial's stimulus (-1: none)
   int choice;      // -1 undecided
   bool flag;
+  uint32_t next_sample;  // time-course variant: next sample step
+};
+
+// Time-course sums.  A sample adds the count and the fixed-point values
+// q(v) = round-half-even(v 2^32) (clamped to +-2^62) of x0, x1, x0^2, x1^2
+// and comp (x0 x1), with two's-complement 64-bit sums: integer additions, so
+// the totals do not depend on the order in which runs arrive.
+__device__ __forceinline__ uint64_t tc_quant(double v) {
+  const double lim = 4611686018427387904.0;  // 2^62
+  double t = __builtin_rint(v * 4294967296.0);
+  t = t > lim ? lim : t;
+  t = t < -lim ? -lim : t;
+  return (uint64_t)(int64_t)t;
+}
+
+__device__ __forceinline__ void tc_add(unsigned long long* w, double x0, double x1, double comp) {
+  atomicAdd(&w[0], 1ull);
+  atomicAdd(&w[1], (unsigned long long)tc_quant(x0));
+  atomicAdd(&w[2], (unsigned long long)tc_quant(x1));
+  atomicAdd(&w[3], (unsigned long long)tc_quant(x0 * x0));
+  atomicAdd(&w[4], (unsigned long long)tc_quant(x1 * x1));
+  atomicAdd(&w[5], (unsigned long long)tc_quant(comp * (x0 * x1)));
+}
+
+// Per-step hooks of the mechanisms.  NoSample compiles to nothing; Sample
+// adds the state after step n when n is the lane's next sample step, into the
+// workgroup's LDS window (the time-course block after the settings' records)
+// or, in direct mode, into global memory.
+struct NoSample {
+  __device__ __forceinline__ void operator()(Lane&, double, double) const {}
+};
+
+struct Sample {
+  unsigned long long* base;  // [window or n_settings][K][kTcWords]
+  uint32_t s_lo, every, K;
+  double comp;
+  __device__ __forceinline__ void operator()(Lane& L, double x0, double x1) const {
+    if (__builtin_expect(L.n == L.next_sample, 0)) {
+      L.next_sample += every;
+      const uint32_t k = L.n / every - 1u;
+      tc_add(base + ((uint64_t)(L.s - s_lo) * K + k) * kTcWords, x0, x1, comp);
+    }
+  }
 };
 
 __device__ __forceinline__ bool near_th(double q, double th, double eps) {
@@ -116,6 +161,17 @@ __device__ void flush(const SimArgs& a, const uint32_t* lds, uint32_t s_lo) {
     }
     if (v) atomicAdd(dst, v);
   }
+  if (a.tc) {
+    const uint32_t per_tc = a.tc_k * kTcWords;
+    const unsigned long long* src =
+        (const unsigned long long*)(lds + a.window * rec_words(a.n_bins));
+    for (uint32_t i = threadIdx.x; i < a.window * per_tc; i += blockDim.x) {
+      const uint32_t w = i / per_tc;
+      if ((uint64_t)s_lo + w >= a.n_settings) continue;
+      const unsigned long long v = src[i];
+      if (v) atomicAdd((unsigned long long*)&a.tc[(uint64_t)s_lo * per_tc + i], v);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -139,11 +195,13 @@ struct DDM {
   }
 
   // guard = thresh - 2 eps: nearer the origin no bound is within flag distance
+  template <class H>
   __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, double z, float zf, float af,
-                                      float bf, double guard) {
+                                      float bf, double guard, const H& hook) {
     if (PREC == CM_FP64) x = (x + a_step) + A.b * z;
     else x = x + (double)fmaf(bf, zf, af);
     L.n += 1;
+    hook(L, x, 0.0);
     // one comparison per step; the exact tests run only within 2 eps of a bound
     if (__builtin_expect(fabs(x) >= guard, 0)) {
       const double th = A.thresh;
@@ -155,8 +213,9 @@ struct DDM {
     return true;
   }
 
+  template <class H>
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
-                                          int pairs) {
+                                          int pairs, const H& hook) {
     const float af = (float)a_step, bf = (float)A.b;
     const double guard = A.thresh - 2.0 * A.flag_eps;
     for (int p = 0; p < pairs; ++p) {
@@ -165,8 +224,8 @@ struct DDM {
       float f0 = 0, f1 = 0;
       if (PREC == CM_FP64) normals64(w, z0, z1);
       else normals32(w, f0, f1);
-      if (!one(A, L, z0, f0, af, bf, guard)) return false;
-      if (!one(A, L, z1, f1, af, bf, guard)) return false;
+      if (!one(A, L, z0, f0, af, bf, guard, hook)) return false;
+      if (!one(A, L, z1, f1, af, bf, guard, hook)) return false;
     }
     return true;
   }
@@ -191,8 +250,9 @@ struct LCA {
     L.target = A.correct[stim];
   }
 
+  template <class H>
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
-                                          int steps) {
+                                          int steps, const H& hook) {
     const double th = A.thresh, eps = A.flag_eps, guard = th - 2.0 * eps;
     for (int k = 0; k < steps; ++k) {
       const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
@@ -219,6 +279,7 @@ struct LCA {
       x0 = y0;
       x1 = y1;
       L.n += 1;
+      hook(L, x0, x1);
       // one comparison per step; the exact tests run only within 2 eps of
       // the threshold, where a unit can be within flag distance or across
       const double mx = x0 > x1 ? x0 : x1;
@@ -243,7 +304,10 @@ struct LCA {
 
 // One launch covers up to kMaxBatch sweeps of the same kind and precision:
 // workgroups [base[i], base[i+1]) belong to sweep i.
-template <class M>
+// TC: the time-course variant, which also samples the state every
+// tc_every steps (one sweep per launch in practice; the LDS window then holds
+// each setting's time-course block after all the settings' records).
+template <class M, bool TC>
 __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
   uint32_t* lds = (uint32_t*)lds_u64;
@@ -259,10 +323,22 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   const uint32_t T = (uint32_t)a.trials;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
 
-  if (!a.direct)
-    for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
+  if (!a.direct) {
+    const uint32_t words = a.window * (rec_words(a.n_bins) + (TC ? tc_words(a.tc_k) : 0u));
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
+  }
   if (threadIdx.x == 0) next = blockDim.x;
   __syncthreads();
+
+  typename std::conditional<TC, Sample, NoSample>::type hook{};
+  if constexpr (TC) {
+    hook.every = a.tc_every;
+    hook.K = a.tc_k;
+    hook.comp = a.comp;
+    hook.s_lo = a.direct ? 0u : s_lo;
+    hook.base = a.direct ? (unsigned long long*)a.tc
+                         : (unsigned long long*)(lds + a.window * rec_words(a.n_bins));
+  }
 
   M m;
   Lane L;
@@ -275,13 +351,14 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
     L.n = 0;
     L.choice = -1;
     L.flag = false;
+    L.next_sample = a.tc_every;
     m.begin(a, L);
   };
   if (have) setup(off);
 
   while (__any(have)) {
     bool running = have;
-    if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync);
+    if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
     if (have && !running) {
       double st[M::kWidth];
       m.state(st);
@@ -412,16 +489,19 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
 }
 
 template <class M>
-hipError_t launch_model(const LaneBatch& b, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((sim_lane_kernel<M>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
+hipError_t launch_model(const LaneBatch& b, bool tc, size_t lds, hipStream_t st) {
+  if (tc)
+    hipLaunchKernelGGL((sim_lane_kernel<M, true>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
+  else
+    hipLaunchKernelGGL((sim_lane_kernel<M, false>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& b, size_t lds_bytes,
-                           hipStream_t st) {
-  if (b.n < 1 || b.n > kMaxBatch) return hipErrorInvalidValue;
+hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const LaneBatch& b,
+                           size_t lds_bytes, hipStream_t st) {
+  if (b.n < 1 || b.n > kMaxBatch || (scan && tc)) return hipErrorInvalidValue;
   if (kind == CM_DDM && scan) {
     if (precision == CM_FP64)
       hipLaunchKernelGGL((ddm_scan_kernel<CM_FP64>), dim3(b.base[b.n]), dim3(kBlock), lds_bytes, st, b);
@@ -430,10 +510,10 @@ hipError_t launch_sim_lane(int kind, int precision, bool scan, const LaneBatch& 
     return hipGetLastError();
   }
   if (kind == CM_DDM)
-    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, lds_bytes, st)
-                                : launch_model<DDM<CM_FP32_STEP>>(b, lds_bytes, st);
-  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, lds_bytes, st)
-                              : launch_model<LCA<CM_FP32_STEP>>(b, lds_bytes, st);
+    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, tc, lds_bytes, st)
+                                : launch_model<DDM<CM_FP32_STEP>>(b, tc, lds_bytes, st);
+  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, lds_bytes, st)
+                              : launch_model<LCA<CM_FP32_STEP>>(b, tc, lds_bytes, st);
 }
 
 }  // namespace cm

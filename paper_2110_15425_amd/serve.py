@@ -5,10 +5,12 @@ the device-memory budget and a free stream allow, groups the admitted
 requests of one tick into batched launches (``cm_launch_batch``: sweeps of
 the same kind and precision share one simulation kernel), and puts each
 group on its own stream, so work from different requests overlaps on the
-device while earlier groups are still running.  Inputs stay resident on the
-device from admission to completion; only the small integer results come
-back, through pinned host buffers, and a request's latency is measured from
-its arrival to the moment its results are on the host.
+device while earlier groups are still running.  The streams, their
+completion events and the result copies belong to libcm's serving queue
+(``cm_submit`` / ``cm_poll``).  Inputs stay resident on the device from
+admission to completion; only the small integer results come back, through
+pinned host buffers, and a request's latency is measured from its arrival to
+the moment its results are on the host.
 
 Results do not depend on what else is in flight: every random number is
 keyed by the request's own (seed, setting, trial, step) and every reduction
@@ -117,41 +119,33 @@ class Scheduler:
 
 
 class GpuBackend:
-    """Device side of the server: one HIP stream per slot, batched launches,
-    asynchronous copies of the results into pinned host memory."""
+    """Device side of the server: libcm's serving queue (``cm_submit`` /
+    ``cm_poll``) with one slot per scheduler stream.  Inputs are written on
+    the current torch stream, which the slot waits for; results come back
+    by asynchronous copies into pinned host memory enqueued by the library
+    behind the batch."""
 
     def __init__(self, handle, n_streams=4):
         import torch
         self.torch = torch
         self.h = handle
-        # all streams at the default priority
-        self.streams = [torch.cuda.Stream(device=handle.device) for _ in range(n_streams)]
+        cm.serve_config(handle, n_streams)
 
     @staticmethod
     def clock():
         return time.perf_counter()
 
     def launch(self, si, ws):
-        torch = self.torch
-        st = self.streams[si]
-        with torch.cuda.stream(st):
-            ds = [cm.DeviceSweep(self.h, w) for w in ws]
-            cm.launch_batch(self.h, ds, stream=st)
-            host = []
-            for d in ds:
-                hh = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
-                      for k, v in (("hist", d.hist), ("stats", d.stats), ("score", d.score),
-                                   ("best", d.best)) if v is not None}
-                for k, t in hh.items():
-                    t.copy_(getattr(d, k), non_blocking=True)
-                host.append(hh)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        return (ev, ds, host)
+        ds = [cm.DeviceSweep(self.h, w) for w in ws]
+        host = [cm.host_buffers(d) for d in ds]
+        ticket = cm.submit(self.h, ds, host)
+        if ticket is None:  # the scheduler frees a slot only after its ticket is done
+            raise RuntimeError("libcm reports every serving slot busy")
+        return (ticket, ds, host)
 
     def poll(self, token):
-        ev, ds, host = token
-        if not ev.query():
+        ticket, ds, host = token
+        if not cm.poll(self.h, ticket):
             return None
         out = []
         for hh in host:

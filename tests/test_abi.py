@@ -118,3 +118,9 @@ def test_null_arguments():
     assert L.cm_workspace_bytes(C.byref(m), C.byref(s), None) == cm.E_INVALID
     assert L.cm_launch(None, C.byref(m), C.byref(s), None, None, 0, None) == cm.E_INVALID
     assert L.cm_create(0, None) == cm.E_INVALID
+    t = C.c_uint64(0)
+    assert L.cm_submit(None, 1, C.byref(m), C.byref(s), None, None, None, None, None,
+                       C.byref(t)) == cm.E_INVALID
+    d = C.c_int(0)
+    assert L.cm_poll(None, 1, C.byref(d)) == cm.E_INVALID
+    assert L.cm_serve_config(None, 4) == cm.E_INVALID

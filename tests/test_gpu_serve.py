@@ -30,3 +30,65 @@ def test_budget_smaller_than_mix_still_completes():
     biggest = max(serve.request_bytes(w) for _, w in mix)
     done = serve.run_mix(h, mix, budget_bytes=biggest + 1, n_streams=2)
     assert len(done) == 16
+
+
+def test_submit_poll_matches_launch():
+    """cm_submit / cm_poll: the host copies it enqueues hold the same results as
+    a plain launch, for a mixed batch of kinds on several slots."""
+    from paper_2110_15425_amd import workloads as W
+    h = cm.Handle(0)
+    cm.serve_config(h, 3)
+    groups = [[W.ddm(trials=3000, seed=3), W.conflict(trials=200, seed=4, precision=W.FP32_STEP)],
+              [W.grid_search(trials=20, seed=5)],
+              [W.rnn(trials=256, seed=6, precision=W.BF16_PROJ), W.ddm(trials=500, seed=7)]]
+    tickets = []
+    for ws in groups:
+        ds = [cm.DeviceSweep(h, w) for w in ws]
+        host = [cm.host_buffers(d) for d in ds]
+        t = cm.submit(h, ds, host)
+        assert t is not None and t > 0
+        tickets.append((t, ws, ds, host))
+    import time
+    t0 = time.time()
+    pending = list(tickets)
+    while pending:
+        pending = [x for x in pending if not cm.poll(h, x[0])]
+        assert time.time() - t0 < 60
+    for t, ws, ds, host in tickets:
+        assert cm.poll(h, t)  # stays done
+        for w, hh in zip(ws, host):
+            alone = cm.run(w, handle=h)
+            for k, v in hh.items():
+                got = v.numpy().view(np.uint64) if k in ("hist", "stats") else v.numpy()
+                assert np.array_equal(got, alone[k]), (k, int(w["kind"]))
+
+
+def test_submit_reports_busy_slots():
+    """With one slot held by unfinished work, a second submit is refused with
+    CM_E_BUSY (nothing enqueued) and succeeds once the first is done."""
+    import time
+    import torch
+    from paper_2110_15425_amd import workloads as W
+    h = cm.Handle(0)
+    cm.serve_config(h, 1)
+    d1 = cm.DeviceSweep(h, W.ddm(trials=2000, seed=1))
+    d2 = cm.DeviceSweep(h, W.ddm(trials=2000, seed=2))
+    producer = torch.cuda.Stream()
+    with torch.cuda.stream(producer):
+        torch.cuda._sleep(200_000_000)  # keeps the producer, and so the slot, busy
+    t1 = cm.submit(h, [d1], producer=producer)
+    assert t1 is not None
+    assert cm.submit(h, [d2]) is None
+    assert not cm.poll(h, t1)
+    t0 = time.time()
+    while not cm.poll(h, t1):
+        assert time.time() - t0 < 60
+    t2 = cm.submit(h, [d2])
+    assert t2 is not None and t2 > t1
+    while not cm.poll(h, t2):
+        assert time.time() - t0 < 60
+    for d, seed in ((d1, 1), (d2, 2)):
+        alone = cm.run(W.ddm(trials=2000, seed=seed), handle=h)
+        assert np.array_equal(d.results()["hist"], alone["hist"])
+    with pytest.raises(cm.CmError):
+        cm.poll(h, t2 + 100)
