@@ -170,7 +170,7 @@ void cmo_conflict_correct(const double *wt, double gain, double bias, int32_t co
 
 int cmo_state_width(const cmo_model *m) {
   if (m->kind == CMO_DDM) return 1;
-  if (m->kind == CMO_LCA) return 2;
+  if (m->kind == CMO_LCA || m->kind == CMO_LOOP) return 2;
   return 2 + m->n_units;
 }
 
@@ -288,13 +288,33 @@ static run_out run_lca(const cmo_model *m, const cmo_sweep *s, int64_t setting,
 typedef struct {
   double *WT;  /* FP64 mode */
   float *WTf;  /* FP32 / BF16 modes: float(W), bf16-rounded in BF16 mode */
+  double *loop_drive; /* closed loop: drive [allocation][stimulus][2] */
+  int32_t correct[9];
 } rnn_ctx;
+
+static double loop_level(double amax, uint32_t L, uint32_t i) {
+  return L == 1 ? amax : (amax * (double)i) / (double)(L - 1);
+}
 
 static void rnn_ctx_init(const cmo_model *m, rnn_ctx *c) {
   const int nu = m->n_units;
   const double *W = m->weights;
   c->WT = NULL;
   c->WTf = NULL;
+  c->loop_drive = NULL;
+  if (m->kind == CMO_LOOP) {
+    /* the drive of every allocation, evaluated once per sweep (loop-invariant) */
+    const uint32_t L = (uint32_t)m->params[CMO_LOOP_LEVELS], J = L * L;
+    const double amax = m->params[CMO_LOOP_AMAX];
+    c->loop_drive = malloc(sizeof(double) * (size_t)J * 18);
+    for (uint32_t j = 0; j < J; ++j)
+      cmo_conflict_drive(m->weights, m->params[CMO_LCA_HID_GAIN], m->params[CMO_LCA_HID_BIAS],
+                         m->params[CMO_LCA_OFFSET], loop_level(amax, L, j / L),
+                         loop_level(amax, L, j % L), (double(*)[2])(c->loop_drive + 18 * (size_t)j));
+    cmo_conflict_correct(m->weights, m->params[CMO_LCA_HID_GAIN], m->params[CMO_LCA_HID_BIAS],
+                         c->correct);
+    return;
+  }
   if (m->kind != CMO_RNN) return;
   if (m->precision == CMO_FP64) {
     c->WT = malloc(sizeof(double) * (size_t)nu * nu);
@@ -313,6 +333,7 @@ static void rnn_ctx_init(const cmo_model *m, rnn_ctx *c) {
 static void rnn_ctx_free(rnn_ctx *c) {
   free(c->WT);
   free(c->WTf);
+  free(c->loop_drive);
 }
 
 static run_out run_rnn(const cmo_model *m, const cmo_sweep *s, const rnn_ctx *ctx,
@@ -438,10 +459,116 @@ static run_out run_rnn(const cmo_model *m, const cmo_sweep *s, const rnn_ctx *ct
   return o;
 }
 
+/* One LCA step from state x with drive in and the normals of block w, in the
+ * model's precision (the same arithmetic as run_lca), NONNEG clipping
+ * included. */
+static void loop_step(const cmo_model *m, const double x[2], const double in[2], const uint32_t w[4],
+                      double y[2]) {
+  double dt = param(m, CMO_LCA_DT), leak = param(m, CMO_LCA_LEAK);
+  double comp = param(m, CMO_LCA_COMP), b = param(m, CMO_LCA_NOISE) * sqrt(dt);
+  if (m->precision == CMO_FP64) {
+    double z[2];
+    cmo_normals64(w, z);
+    cmo_lca_update(x, in, leak, comp, dt, b, z, y);
+  } else {
+    float z[2];
+    cmo_normals32(w, z);
+    float inf0 = (float)in[0], inf1 = (float)in[1];
+    float leakf = (float)leak, compf = (float)comp, dtf = (float)dt, bf = (float)b;
+    float xf0 = (float)x[0], xf1 = (float)x[1];
+    float inc0 = (((inf0 - leakf * xf0) - compf * xf1) * dtf) + bf * z[0];
+    float inc1 = (((inf1 - leakf * xf1) - compf * xf0) * dtf) + bf * z[1];
+    y[0] = x[0] + (double)inc0;
+    y[1] = x[1] + (double)inc1;
+  }
+  if (param(m, CMO_LCA_NONNEG) != 0.0) {
+    if (y[0] < 0.0) y[0] = 0.0;
+    if (y[1] < 0.0) y[1] = 0.0;
+  }
+}
+
+/* Closed-loop control of the conflict network: before every step the control
+ * node evaluates each allocation (c_A, c_B) of the L x L level grid by M
+ * sampled one-step look-aheads of the accumulators (each with its own random
+ * stream), scores it as cost * (c_A^2 + c_B^2) minus the mean gain in
+ * evidence for the correct response, x_c - x_w, and picks the lowest score
+ * (ties: a random pick, the smallest Philox priority); the step itself then
+ * runs with the chosen allocation on the run's own stream.  State carries
+ * across steps, and the search is nested inside each step, as in the
+ * predator-prey control loop (Sec. 2.1); evaluations of the allocations and
+ * samples are independent (Sec. 3.6).  A run is flagged when the best and
+ * second-best scores differ by less than flag_eps without being equal. */
+static run_out run_loop(const cmo_model *m, const cmo_sweep *s, const rnn_ctx *ctx,
+                        int64_t setting, uint64_t trial, double *state, double *traj) {
+  const double th = param(m, CMO_LCA_THRESH), eps = s->flag_eps;
+  const uint32_t L = (uint32_t)param(m, CMO_LOOP_LEVELS), J = L * L;
+  const uint32_t M = (uint32_t)param(m, CMO_LOOP_SAMPLES);
+  const double amax = param(m, CMO_LOOP_AMAX);
+  const double kappa = signal(m, s, setting, 0, param(m, CMO_LOOP_COST));
+  const int stim = (int)(trial % 9u);
+  const int c = ctx->correct[stim], o = 1 - c;
+  const uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
+  double x[2] = {0.0, 0.0};
+  run_out out = {-1, s->max_steps, 0};
+  for (uint32_t n = 1; n <= s->max_steps; ++n) {
+    double bestV = INFINITY, secondV = INFINITY;
+    uint32_t best = 0, best_prio = 0;
+    for (uint32_t j = 0; j < J; ++j) {
+      const double *in = ctx->loop_drive + (18 * (size_t)j + 2 * (size_t)stim);
+      double gsum = 0.0;
+      for (uint32_t mm = 0; mm < M; ++mm) {
+        uint32_t w[4];
+        block(s->seed, n - 1, trial, (uint64_t)setting, CMO_STREAM_LOOK | (j * M + mm), w);
+        double y[2];
+        loop_step(m, x, in, w, y);
+        gsum = gsum + ((y[c] - y[o]) - (x[c] - x[o]));
+      }
+      const double cA = loop_level(amax, L, j / L), cB = loop_level(amax, L, j % L);
+      const double V = kappa * (cA * cA + cB * cB) - gsum / (double)M;
+      uint32_t ctr[4] = {n - 1, (uint32_t)trial, (uint32_t)setting, CMO_STREAM_PICK | j}, pw[4];
+      if (V < bestV) {
+        secondV = bestV;
+        bestV = V;
+        best = j;
+        cmo_philox4x32_10(ctr, key, pw);
+        best_prio = pw[0];
+      } else if (V == bestV) {
+        secondV = V;
+        cmo_philox4x32_10(ctr, key, pw);
+        if (pw[0] < best_prio) { /* allocations visited ascending: equal priority keeps the smaller */
+          best = j;
+          best_prio = pw[0];
+        }
+      } else if (V < secondV) {
+        secondV = V;
+      }
+    }
+    if (secondV > bestV && secondV - bestV < eps) out.flag = 1;
+    uint32_t w[4];
+    block(s->seed, n - 1, trial, (uint64_t)setting, 0, w);
+    double y[2];
+    loop_step(m, x, ctx->loop_drive + (18 * (size_t)best + 2 * (size_t)stim), w, y);
+    x[0] = y[0];
+    x[1] = y[1];
+    if (traj) { traj[2 * (n - 1)] = x[0]; traj[2 * (n - 1) + 1] = x[1]; }
+    if (near(x[0], th, eps) || near(x[1], th, eps)) out.flag = 1;
+    double mx = x[0] > x[1] ? x[0] : x[1];
+    if (mx >= th) {
+      out.choice = (x[1] > x[0]) ? 1 : 0;
+      if (fabs(x[0] - x[1]) < eps) out.flag = 1;
+      out.steps = n;
+      break;
+    }
+  }
+  if (state) { state[0] = x[0]; state[1] = x[1]; }
+  return out;
+}
+
 static run_out run_one(const cmo_model *m, const cmo_sweep *s, const rnn_ctx *ctx,
                        int64_t setting, uint64_t trial, double *state, double *traj) {
   if (m->kind == CMO_DDM) return run_ddm(m, s, setting, trial, state, traj);
   if (m->kind == CMO_LCA) return run_lca(m, s, setting, trial, state, traj);
+  if (m->kind == CMO_LOOP) return run_loop(m, s, ctx, setting, trial, state, traj);
   return run_rnn(m, s, ctx, setting, trial, state, traj);
 }
 
@@ -466,6 +593,15 @@ static int invalid(const cmo_model *m, const cmo_sweep *s) {
     if (!m->weights || m->n_weights < 40 || m->precision == CMO_BF16_PROJ) return 1;
     const double *p = m->params;
     if (!(p[CMO_LCA_DT] > 0) || !(p[CMO_LCA_NOISE] >= 0) || !(p[CMO_LCA_THRESH] > 0)) return 1;
+  } else if (m->kind == CMO_LOOP) {
+    if (m->n_params < CMO_LOOP_NPARAM || m->n_stimuli != 9 || m->n_units != 2) return 1;
+    if (m->n_signals > 1 || !m->weights || m->n_weights < 40) return 1;
+    if (m->precision == CMO_BF16_PROJ) return 1;
+    const double *p = m->params;
+    if (!(p[CMO_LCA_DT] > 0) || !(p[CMO_LCA_NOISE] >= 0) || !(p[CMO_LCA_THRESH] > 0)) return 1;
+    const double L = p[CMO_LOOP_LEVELS], M = p[CMO_LOOP_SAMPLES];
+    if (!(L >= 1 && L <= 4096 && L == floor(L)) || !(M >= 1 && M <= 4096 && M == floor(M))) return 1;
+    if (L * L * M >= 1073741824.0 || !(p[CMO_LOOP_AMAX] >= 0)) return 1;
   } else if (m->kind == CMO_RNN) {
     if (m->n_params < CMO_RNN_NPARAM || m->n_stimuli != 1 || m->n_signals > 1) return 1;
     if (m->n_units < 2 || m->n_units > 1024 || (m->n_units & 1)) return 1;
@@ -483,7 +619,7 @@ static int invalid(const cmo_model *m, const cmo_sweep *s) {
 static void correct_table(const cmo_model *m, int32_t correct[9]) {
   for (int i = 0; i < 9; ++i) correct[i] = -1;
   if (m->kind == CMO_DDM) correct[0] = 1;
-  else if (m->kind == CMO_LCA)
+  else if (m->kind == CMO_LCA || m->kind == CMO_LOOP)
     cmo_conflict_correct(m->weights, m->params[CMO_LCA_HID_GAIN], m->params[CMO_LCA_HID_BIAS],
                          correct);
 }

@@ -24,7 +24,7 @@ extern "C" {
 #endif
 
 /* model kinds */
-enum { CMO_DDM = 0, CMO_LCA = 1, CMO_RNN = 2 };
+enum { CMO_DDM = 0, CMO_LCA = 1, CMO_RNN = 2, CMO_LOOP = 3 };
 /* precision modes */
 enum { CMO_FP64 = 0, CMO_FP32_STEP = 1, CMO_BF16_PROJ = 2 };
 
@@ -36,6 +36,11 @@ enum { CMO_LCA_DT = 0, CMO_LCA_LEAK, CMO_LCA_COMP, CMO_LCA_NOISE,
        CMO_LCA_NONNEG, CMO_LCA_T0, CMO_LCA_NPARAM };
 enum { CMO_RNN_DT = 0, CMO_RNN_NOISE, CMO_RNN_THRESH, CMO_RNN_INPUT_GAIN,
        CMO_RNN_T0, CMO_RNN_NPARAM };
+/* Closed-loop control of the conflict network: the LCA parameters, then the
+ * control search (levels per signal L, top level A_max, look-ahead samples M,
+ * control-cost weight). */
+enum { CMO_LOOP_LEVELS = CMO_LCA_NPARAM, CMO_LOOP_AMAX, CMO_LOOP_SAMPLES, CMO_LOOP_COST,
+       CMO_LOOP_NPARAM };
 
 /* statistics per setting */
 enum { CMO_ST_DEC0 = 0, CMO_ST_DEC1, CMO_ST_UNDEC, CMO_ST_CORRECT,
@@ -45,10 +50,12 @@ enum { CMO_ST_DEC0 = 0, CMO_ST_DEC1, CMO_ST_UNDEC, CMO_ST_CORRECT,
 /* Random stream ids (counter word 3). */
 #define CMO_STREAM_DRIVE 0x40000000u
 #define CMO_STREAM_TIE 0xFFFFFFFFu
+#define CMO_STREAM_LOOK 0x80000000u /* | (allocation * M + sample), < 2^30 */
+#define CMO_STREAM_PICK 0xC0000000u /* | allocation */
 
 typedef struct {
   int32_t kind, precision;
-  int32_t n_units;     /* DDM 1, LCA 2, RNN n (even, <= 1024) */
+  int32_t n_units;     /* DDM 1, LCA 2, RNN n (even, <= 1024), LOOP 2 */
   int32_t n_stimuli;   /* DDM 1, LCA 9, RNN 1 */
   int32_t n_signals;   /* DDM 0/1 (drift), LCA 0/2 (cA,cB), RNN 0/1 (gain) */
   const double *params;

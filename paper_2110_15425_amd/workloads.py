@@ -10,12 +10,14 @@ these synthetic models stand in for them with the shapes of its workloads:
 a single drift-diffusion decision (the DDM nodes of the extended Stroop
 models), a two-pathway conflict network feeding a leaky competing
 accumulator (Stroop/multitasking), a control grid search over two signals
-(the Control node's allocation search), and a recurrent logistic rate
-network (a scaled analogue of the Necker-cube networks).
+(the Control node's allocation search), the same network under closed-loop
+control re-optimised before every step (the control loop of the
+predator-prey model), and a recurrent logistic rate network (a scaled
+analogue of the Necker-cube networks).
 """
 import numpy as np
 
-DDM, LCA, RNN = 0, 1, 2
+DDM, LCA, RNN, LOOP = 0, 1, 2, 3
 FP64, FP32_STEP, BF16_PROJ = 0, 1, 2
 
 # parameter slots, one enum per kind (string keys become fixed offsets)
@@ -23,8 +25,9 @@ DDM_P = dict(dt=0, drift=1, noise=2, thresh=3, start=4, t0=5)
 LCA_P = dict(dt=0, leak=1, comp=2, noise=3, thresh=4, offset=5, hid_gain=6, hid_bias=7,
              nonneg=8, t0=9)
 RNN_P = dict(dt=0, noise=1, thresh=2, input_gain=3, t0=4)
+LOOP_P = dict(LCA_P, levels=10, amax=11, samples=12, cost=13)
 
-KIND_NAMES = {DDM: "ddm", LCA: "conflict_lca", RNN: "rate_rnn"}
+KIND_NAMES = {DDM: "ddm", LCA: "conflict_lca", RNN: "rate_rnn", LOOP: "conflict_loop"}
 PREC_NAMES = {FP64: "fp64", FP32_STEP: "fp32_step", BF16_PROJ: "bf16_proj"}
 
 
@@ -115,6 +118,22 @@ def rnn(trials=65_536, seed=1, weights_seed=7, n_units=256, dt=0.05, noise=0.05,
     w = rnn_weights(n_units, weights_seed) if weights is None else np.asarray(weights, np.float64)
     grid = None if gains is None else np.asarray(gains, np.float64).reshape(-1, 1)
     return _base(RNN, precision, p, w, n_units, 1, grid, trials, seed, max_steps, n_bins, **kw)
+
+
+def control_loop(trials=1000, seed=1, weights_seed=11, levels=8, amax=5.0, samples=4, cost=0.01,
+                 costs=None, leak=0.5, comp=1.0, noise=0.1, thresh=0.8, dt=0.1, max_steps=1000,
+                 n_bins=100, hid_gain=1.0, hid_bias=-4.0, offset=0.0, nonneg=0.0, t0=0.0,
+                 precision=FP64, weights=None, **kw):
+    """Closed-loop control of the conflict network: before every step each run
+    searches the levels x levels grid of control allocations (c_A, c_B) in
+    [0, amax]^2 with ``samples`` look-ahead draws per allocation.  ``costs``
+    (optional) gives one setting per control-cost weight."""
+    p = _params(LOOP_P, dt=dt, leak=leak, comp=comp, noise=noise, thresh=thresh, offset=offset,
+                hid_gain=hid_gain, hid_bias=hid_bias, nonneg=nonneg, t0=t0, levels=levels,
+                amax=amax, samples=samples, cost=cost)
+    w = conflict_weights(weights_seed) if weights is None else np.asarray(weights, np.float64)
+    grid = None if costs is None else np.asarray(costs, np.float64).reshape(-1, 1)
+    return _base(LOOP, precision, p, w, 2, 9, grid, trials, seed, max_steps, n_bins, **kw)
 
 
 def with_(w, **changes):
