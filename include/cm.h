@@ -59,7 +59,8 @@ typedef enum {
 typedef enum {
   CM_DDM = 0,          /* drift-diffusion, Euler-Maruyama, bounds +-theta */
   CM_CONFLICT_LCA = 1, /* two-pathway logistic network -> 2-unit leaky competing accumulator */
-  CM_RATE_RNN = 2      /* n-unit logistic recurrent rate network with a 2-unit readout */
+  CM_RATE_RNN = 2,     /* n-unit logistic recurrent rate network with a 2-unit readout */
+  CM_CONFLICT_LOOP = 3 /* the conflict LCA under closed-loop control re-optimised every step */
 } cm_kind;
 
 /* Arithmetic modes.  CM_FP64: everything in double.  CM_FP32_STEP: normals,
@@ -76,6 +77,20 @@ enum { CM_LCA_DT = 0, CM_LCA_LEAK, CM_LCA_COMP, CM_LCA_NOISE, CM_LCA_THRESH,
        CM_LCA_NPARAM };
 enum { CM_RNN_DT = 0, CM_RNN_NOISE, CM_RNN_THRESH, CM_RNN_INPUT_GAIN, CM_RNN_T0,
        CM_RNN_NPARAM };
+/* Closed loop: the conflict LCA's parameters, then the control search.
+ * Before every step the control node scores each allocation (c_A, c_B) of
+ * the L x L grid of levels a_i = A_max i / (L - 1) (A_max when L = 1) by M
+ * one-step look-aheads, each on its own random stream, as
+ * COST * (c_A^2 + c_B^2) - mean over samples of the change in x_c - x_w
+ * (c the correct response of the trial's stimulus), takes the lowest score
+ * (exact ties: a random pick) and runs the step with it on the run's own
+ * stream: the control loop nested in every time step of the predator-prey
+ * model (Distill, Sec. 2.1), allocations and samples evaluated in parallel
+ * (Sec. 3.6).  Requires 1 <= L, M <= 4096 integers and L*L*M < 2^30.  A run
+ * is also flagged when its best and second-best scores differ by less than
+ * flag_eps without being equal. */
+enum { CM_LOOP_LEVELS = CM_LCA_NPARAM, CM_LOOP_AMAX, CM_LOOP_SAMPLES, CM_LOOP_COST,
+       CM_LOOP_NPARAM };
 
 /* Per-setting statistics, CM_NSTAT uint64 words per setting. */
 enum { CM_ST_DEC0 = 0, CM_ST_DEC1, CM_ST_UNDEC, CM_ST_CORRECT, CM_ST_SUMN0,
@@ -84,17 +99,18 @@ enum { CM_ST_DEC0 = 0, CM_ST_DEC1, CM_ST_UNDEC, CM_ST_CORRECT, CM_ST_SUMN0,
 /*
  * The model.
  *  kind, precision  cm_kind, cm_precision.
- *  n_units          DDM 1; conflict LCA 2; rate network n, even, 64 <= n <= 256,
- *                   n a multiple of 64.
+ *  n_units          DDM 1; conflict LCA and its closed loop 2; rate network n,
+ *                   64 <= n <= 256, n a multiple of 64.
  *  n_stimuli        DDM 1; conflict LCA 9 (pairs (a, b) of one-hot inputs,
  *                   trial t uses stimulus t mod 9, as the trial loop of
  *                   Sec. 2.2 cycles through its input list); rate network 1.
  *  n_signals        signals per grid setting.  DDM 0 or 1 (overrides the
  *                   drift); conflict LCA 0 or 2 (control gains c_A, c_B,
- *                   1 when absent); rate network 0 or 1 (overrides the
- *                   input gain).
+ *                   1 when absent); closed loop 0 or 1 (overrides the
+ *                   control-cost weight); rate network 0 or 1 (overrides
+ *                   the input gain).
  *  params           HOST, n_params doubles in the kind's enum order.
- *  weights          DEVICE, row-major blocks.  Conflict LCA: W_A[4x3],
+ *  weights          DEVICE, row-major blocks.  Conflict LCA and loop: W_A[4x3],
  *                   W_B[4x3], O_A[2x4], O_B[2x4] (40 doubles).  Rate
  *                   network: W[n x n] then R[2 x n].  DDM: unused (NULL).
  */

@@ -146,7 +146,7 @@ def workspace_bytes(w):
 
 
 def state_width(w):
-    return {0: 1, 1: 2}.get(int(w["kind"]), 2 + int(w["n_units"]))
+    return {0: 1, 1: 2, 3: 2}.get(int(w["kind"]), 2 + int(w["n_units"]))
 
 
 class Handle:

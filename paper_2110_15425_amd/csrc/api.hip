@@ -21,7 +21,7 @@ struct cm_handle {
   int device;
   int cu_count;
   size_t lds_per_block;
-  cm_tuning tune[3][3];  // [kind][precision]
+  cm_tuning tune[4][3];  // [kind][precision]
   // kernel timing: event pairs recorded around simulation kernels
   uint32_t* host_count = nullptr;  // pinned, for the unfused step loop
   bool prof = false;
@@ -78,6 +78,10 @@ Layout layout(const cm_model* m, const cm_sweep* s) {
   off = align_up(off + 16 * sizeof(int32_t), kWorkspaceAlign);
   L.drive = off;
   if (m->kind == CM_CONFLICT_LCA) off = align_up(off + s->n_settings * 9u * 2u * sizeof(double), kWorkspaceAlign);
+  if (m->kind == CM_CONFLICT_LOOP) {
+    const uint64_t lv = (uint64_t)m->params[CM_LOOP_LEVELS];  // validated before any layout is used
+    off = align_up(off + lv * lv * 9u * 2u * sizeof(double), kWorkspaceAlign);
+  }
   L.wfrag = off;
   if (m->kind == CM_RATE_RNN) {
     const uint64_t elem = m->precision == CM_FP64 ? sizeof(double) : 2u;
@@ -170,6 +174,26 @@ cm_status check_model_sweep(const cm_model* m, const cm_sweep* s) {
       if (m->precision == CM_FP32_STEP)
         return fail(CM_E_UNSUPPORTED, "rate network: use CM_FP64 or CM_BF16_PROJ");
       break;
+    case CM_CONFLICT_LOOP: {
+      if (m->n_params < CM_LOOP_NPARAM) return fail(CM_E_INVALID, "closed loop needs %d params", CM_LOOP_NPARAM);
+      if (m->n_units != 2 || m->n_stimuli != 9 || m->n_signals > 1)
+        return fail(CM_E_INVALID, "closed loop: n_units 2, n_stimuli 9, n_signals 0 or 1");
+      if (!m->weights || m->n_weights < 40) return fail(CM_E_INVALID, "closed loop needs 40 weights");
+      if (!aligned(m->weights, 8)) return fail(CM_E_INVALID, "weights must be 8-byte aligned");
+      if (!(p[CM_LCA_DT] > 0) || !isfinite(p[CM_LCA_DT])) return fail(CM_E_INVALID, "dt must be > 0");
+      if (!(p[CM_LCA_NOISE] >= 0) || !isfinite(p[CM_LCA_NOISE])) return fail(CM_E_INVALID, "noise must be >= 0");
+      if (!(p[CM_LCA_THRESH] > 0)) return fail(CM_E_INVALID, "threshold must be > 0");
+      for (int i : {(int)CM_LCA_LEAK, (int)CM_LCA_COMP, (int)CM_LCA_OFFSET, (int)CM_LCA_HID_GAIN,
+                    (int)CM_LCA_HID_BIAS, (int)CM_LOOP_COST})
+        if (!isfinite(p[i])) return fail(CM_E_INVALID, "closed-loop parameter %d must be finite", i);
+      const double L = p[CM_LOOP_LEVELS], M = p[CM_LOOP_SAMPLES];
+      if (!(L >= 1 && L <= 4096 && L == floor(L)) || !(M >= 1 && M <= 4096 && M == floor(M)))
+        return fail(CM_E_INVALID, "levels and samples must be integers in [1, 4096]");
+      if (L * L * M >= 1073741824.0) return fail(CM_E_INVALID, "levels^2 * samples must be < 2^30");
+      if (!(p[CM_LOOP_AMAX] >= 0) || !isfinite(p[CM_LOOP_AMAX])) return fail(CM_E_INVALID, "A_max must be finite and >= 0");
+      if (m->precision == CM_BF16_PROJ) return fail(CM_E_UNSUPPORTED, "bf16 projection applies to the rate network only");
+      break;
+    }
     default:
       return fail(CM_E_INVALID, "unknown kind %u", m->kind);
   }
@@ -425,6 +449,19 @@ void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* w
     it.d.drive = (double*)(ws + L.drive);
     it.d.correct = (int32_t*)(ws + L.correct);
     tables = 9 + S * 9u;
+  } else if (m->kind == CM_CONFLICT_LOOP) {
+    const uint32_t lv = (uint32_t)p[CM_LOOP_LEVELS];
+    it.kind = CM_CONFLICT_LCA;  // the same tables, one drive row per allocation
+    it.d.n_settings = (uint64_t)lv * lv;
+    it.d.levels = lv;
+    it.d.amax = p[CM_LOOP_AMAX];
+    it.d.gain = p[CM_LCA_HID_GAIN];
+    it.d.bias = p[CM_LCA_HID_BIAS];
+    it.d.offset = p[CM_LCA_OFFSET];
+    it.d.weights = m->weights;
+    it.d.drive = (double*)(ws + L.drive);
+    it.d.correct = (int32_t*)(ws + L.correct);
+    tables = 9 + it.d.n_settings * 9u;
   }
   it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + it.n_extra + tables;
   ++b.n;
@@ -502,6 +539,52 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_rnn(m->precision, a, groups, stream)) != hipSuccess) return hip_fail(e, "rate-network kernel");
+  if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  return enqueue_score(m, s, r, stream);
+}
+
+cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                            char* ws, const Layout& L, hipStream_t stream) {
+  const double* p = m->params;
+  cm::LoopArgs a{};
+  a.trials = s->trials;
+  a.n_settings = s->n_settings;
+  a.total_runs = s->n_settings * s->trials;
+  a.seed = s->seed;
+  a.max_steps = s->max_steps;
+  a.n_bins = s->n_bins;
+  a.steps_magic = cm::udiv_magic_for(s->max_steps);
+  a.n_signals = m->n_signals;
+  a.L = (uint32_t)p[CM_LOOP_LEVELS];
+  a.J = a.L * a.L;
+  a.M = (uint32_t)p[CM_LOOP_SAMPLES];
+  a.nonneg = p[CM_LCA_NONNEG] != 0.0;
+  a.thresh = p[CM_LCA_THRESH];
+  a.flag_eps = s->flag_eps;
+  a.dt = p[CM_LCA_DT];
+  a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
+  a.leak = p[CM_LCA_LEAK];
+  a.comp = p[CM_LCA_COMP];
+  a.cost = p[CM_LOOP_COST];
+  a.amax = p[CM_LOOP_AMAX];
+  a.grid = s->grid;
+  a.drive = (const double*)(ws + L.drive);
+  a.correct = (const int32_t*)(ws + L.correct);
+  a.hist = r->hist;
+  a.stats = r->stats;
+  a.run_choice = r->run_choice;
+  a.run_step = r->run_step;
+  a.run_flag = r->run_flag;
+  a.run_state = r->run_state;
+  cm_status st = enqueue_prep(m, s, r, ws, L, stream);
+  if (st != CM_OK) return st;
+  const uint64_t teams_per_block = 256u / cm::loop_team_lanes(a.J);
+  const uint64_t want = (a.total_runs + teams_per_block - 1) / teams_per_block;
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * h->cu_count));
+  hipError_t e;
+  ProfScope prof{h, stream};
+  if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = cm::launch_loop(m->precision, a, blocks, stream)) != hipSuccess) return hip_fail(e, "closed-loop kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   return enqueue_score(m, s, r, stream);
 }
@@ -588,7 +671,7 @@ cm_status cm_create(int device_ordinal, cm_handle** out) {
   h->device = device_ordinal;
   h->cu_count = prop.multiProcessorCount;
   h->lds_per_block = prop.sharedMemPerBlock;
-  for (uint32_t k = 0; k < 3; ++k)
+  for (uint32_t k = 0; k < 4; ++k)
     for (uint32_t p = 0; p < 3; ++p) h->tune[k][p] = default_tuning(k, p);
   *out = h;
   return ok();
@@ -724,7 +807,7 @@ cm_status cm_profile_read(cm_handle* h, double* sim_ms, uint64_t* launches) {
 }
 
 cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const cm_tuning* t) {
-  if (!h || !t || kind > 2 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
+  if (!h || !t || kind > 3 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
   cm_tuning v = *t;
   const cm_tuning d = default_tuning(kind, precision);
   if (!v.block) v.block = d.block;
@@ -742,7 +825,7 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
 }
 
 cm_status cm_get_tuning(cm_handle* h, uint32_t kind, uint32_t precision, cm_tuning* t) {
-  if (!h || !t || kind > 2 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
+  if (!h || !t || kind > 3 || precision > 2) return fail(CM_E_INVALID, "bad tuning arguments");
   *t = h->tune[kind][precision];
   return ok();
 }
@@ -791,15 +874,17 @@ cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, cons
   // rate-network sweeps launch one by one; lane-kernel sweeps of one kind and
   // precision share launches of up to kMaxBatch sweeps
   std::vector<uint32_t> group;
-  for (uint32_t kind = 0; kind < 3; ++kind)
+  for (uint32_t kind = 0; kind < 4; ++kind)
     for (uint32_t prec = 0; prec < 3; ++prec) {
       group.clear();
       for (uint32_t i = 0; i < n; ++i)
         if (models[i].kind == kind && models[i].precision == prec) group.push_back(i);
       if (group.empty()) continue;
-      if (kind == CM_RATE_RNN) {
+      if (kind == CM_RATE_RNN || kind == CM_CONFLICT_LOOP) {
         for (uint32_t i : group) {
-          cm_status st = launch_rnn_sweep(h, &models[i], &sweeps[i], &results[i], (char*)workspaces[i], L[i], stream);
+          cm_status st = kind == CM_RATE_RNN
+                             ? launch_rnn_sweep(h, &models[i], &sweeps[i], &results[i], (char*)workspaces[i], L[i], stream)
+                             : launch_loop_sweep(h, &models[i], &sweeps[i], &results[i], (char*)workspaces[i], L[i], stream);
           if (st != CM_OK) return st;
         }
         continue;
@@ -818,7 +903,8 @@ cm_status cm_unfused_workspace_bytes(const cm_model* m, const cm_sweep* s, uint6
   if (!bytes) return fail(CM_E_INVALID, "bytes must not be NULL");
   cm_status st = check_model_sweep(m, s);
   if (st != CM_OK) return st;
-  if (m->kind == CM_RATE_RNN) return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
+  if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
   *bytes = unfused_layout(m, s).total;
   return ok();
 }
@@ -828,7 +914,8 @@ cm_status cm_launch_unfused(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
   cm_status st = check_model_sweep(m, s);
   if (st != CM_OK) return st;
-  if (m->kind == CM_RATE_RNN) return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
+  if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
   if ((st = check_result(m, s, r)) != CM_OK) return st;
   const UnfusedLayout U = unfused_layout(m, s);
   if (!workspace || !aligned(workspace, kWorkspaceAlign))

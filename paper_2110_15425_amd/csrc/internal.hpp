@@ -76,8 +76,10 @@ struct ScoreArgs {
 };
 
 struct DriveArgs {
-  uint64_t n_settings;
+  uint64_t n_settings;  // rows of the drive table (allocations in the closed loop)
   uint32_t n_signals;
+  uint32_t levels;      // closed loop: row j is allocation (level j / L, level j % L)
+  double amax;          // closed loop: top control level
   double gain, bias, offset;
   const double* weights;
   const double* grid;
@@ -151,6 +153,23 @@ struct UnfusedArgs {
   double* run_state;
 };
 
+// Arguments of the closed-loop control kernel.
+struct LoopArgs {
+  uint64_t trials, n_settings, total_runs, seed;
+  uint64_t steps_magic;
+  uint32_t max_steps, n_bins, n_signals, L, J, M, nonneg, pad;
+  double thresh, flag_eps, b, dt, leak, comp, cost, amax;
+  const double* grid;      // [n_settings] control-cost weights, or NULL
+  const double* drive;     // [J][9][2]
+  const int32_t* correct;  // [9]
+  uint64_t* hist;
+  uint64_t* stats;
+  int8_t* run_choice;
+  uint32_t* run_step;
+  uint8_t* run_flag;
+  double* run_state;
+};
+
 // Arguments of the DDM density propagation.
 struct DensityArgs {
   uint64_t n_settings;
@@ -165,6 +184,8 @@ hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const La
                            size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
+uint32_t loop_team_lanes(uint32_t J);
+hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st);
 hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);
 hipError_t launch_rnn(int precision, const RnnArgs& a, uint32_t groups, hipStream_t st);
 hipError_t launch_uf_init(const UnfusedArgs& a, hipStream_t st);

@@ -1,0 +1,203 @@
+// loop.hip -- closed-loop control of the conflict network.
+//
+// Before every step of a run, the control node searches the L x L grid of
+// allocations (c_A, c_B): each allocation is scored by M sampled one-step
+// look-aheads of the leaky competing accumulator (each with its own random
+// stream) as cost * |c|^2 minus the mean gain in evidence x_c - x_w for the
+// correct response, and the lowest score wins (exact ties: the smallest
+// Philox priority, a random pick).  The step then runs with the chosen
+// allocation on the run's own stream, and the state carries to the next
+// search: the control loop nested inside each time step of the Distill
+// paper's predator-prey model (Sec. 2.1), with its allocations and samples
+// evaluated in parallel (Sec. 3.6).
+//
+// Mapping: a team of P lanes (P = 1, 4, 16 or 64, the power of two that
+// covers the L^2 allocations, capped at a wavefront) owns one run at a time.
+// Lane i of the team evaluates allocations i, i + P, ... with all their
+// samples; a butterfly of P-lane shuffles then finds the best (score,
+// priority, allocation) and the second-best score, leaving the same result
+// in every lane.  Every lane of the team then applies the chosen step to its
+// own copy of the state (identical arithmetic, identical bits), so the team
+// never broadcasts and its control flow stays uniform.  Teams take runs in a
+// fixed stride, and a finished run is counted straight into global memory
+// by the team's first lane: a run costs L^2 M look-ahead steps per step, so
+// the atomics are negligible.  The allocation drive table [L^2][9][2] is
+// computed once per sweep by the preparation kernel.
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace cm {
+namespace {
+
+constexpr int kLoopBlock = 256;
+constexpr uint32_t kStreamLook = 0x80000000u;  // | (allocation * M + sample)
+constexpr uint32_t kStreamPick = 0xC0000000u;  // | allocation
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// One LCA step in the model's precision: the arithmetic of the open-loop
+// LCA kernel, so that a one-allocation loop reproduces it bit for bit.
+template <int PREC>
+__device__ __forceinline__ void lca_step(const LoopArgs& a, double x0, double x1, double in0,
+                                         double in1, const Words& w, double& y0, double& y1) {
+  if (PREC == CM_FP64) {
+    double z0, z1;
+    normals64(w, z0, z1);
+    y0 = (x0 + (((in0 - a.leak * x0) - a.comp * x1) * a.dt)) + a.b * z0;
+    y1 = (x1 + (((in1 - a.leak * x1) - a.comp * x0) * a.dt)) + a.b * z1;
+  } else {
+    float z0, z1;
+    normals32(w, z0, z1);
+    const float xf0 = (float)x0, xf1 = (float)x1;
+    const float lf = (float)a.leak, cf = (float)a.comp, df = (float)a.dt, bf = (float)a.b;
+    const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
+    const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
+    y0 = x0 + (double)fmaf(bf, z0, i0 * df);
+    y1 = x1 + (double)fmaf(bf, z1, i1 * df);
+  }
+  if (a.nonneg) {
+    if (y0 < 0.0) y0 = 0.0;
+    if (y1 < 0.0) y1 = 0.0;
+  }
+}
+
+__device__ __forceinline__ double level(const LoopArgs& a, uint32_t i) {
+  return a.L == 1 ? a.amax : (a.amax * (double)i) / (double)(a.L - 1);
+}
+
+// Tie rule among allocations with equal scores: the smaller (Philox priority,
+// allocation) wins.  kNone stands for "no allocation yet".
+__device__ __forceinline__ bool tie_wins(uint32_t j, uint32_t bj, uint32_t k, uint32_t t, uint32_t s,
+                                         uint32_t k0, uint32_t k1) {
+  if (j == bj || j == kNone) return false;
+  if (bj == kNone) return true;
+  const uint32_t pj = philox(k, t, s, kStreamPick | j, k0, k1).w0;
+  const uint32_t pb = philox(k, t, s, kStreamPick | bj, k0, k1).w0;
+  return pj < pb || (pj == pb && j < bj);
+}
+
+template <int PREC, int P>
+__global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
+  const uint32_t j0 = (threadIdx.x & 63u) % (uint32_t)P;
+  const uint32_t teams_per_block = kLoopBlock / P;
+  const uint64_t n_teams = (uint64_t)gridDim.x * teams_per_block;
+  const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+  const uint32_t T = (uint32_t)a.trials, J = a.J, M = a.M, N = a.max_steps;
+  const double th = a.thresh, eps = a.flag_eps;
+  for (uint64_t run = (uint64_t)blockIdx.x * teams_per_block + threadIdx.x / P; run < a.total_runs;
+       run += n_teams) {
+    const uint32_t s = (uint32_t)(run / T), t = (uint32_t)(run - (uint64_t)s * T);
+    const uint32_t stim = t % 9u;
+    const int c = a.correct[stim];
+    const double kappa = a.n_signals ? a.grid[s] : a.cost;
+    double x0 = 0.0, x1 = 0.0;
+    bool flag = false;
+    int choice = -1;
+    uint32_t n = 1;
+    for (; n <= N; ++n) {
+      const uint32_t k = n - 1u;
+      const double dx = c ? x1 - x0 : x0 - x1;  // x_c - x_w
+      double bv = INFINITY, sv = INFINITY;
+      uint32_t bj = kNone;
+      for (uint32_t j = j0; j < J; j += P) {
+        const double* d = a.drive + ((uint64_t)j * 9u + stim) * 2u;
+        const double in0 = d[0], in1 = d[1];
+        double gsum = 0.0;
+        for (uint32_t m = 0; m < M; ++m) {
+          const Words w = philox(k, t, s, kStreamLook | (j * M + m), k0, k1);
+          double y0, y1;
+          lca_step<PREC>(a, x0, x1, in0, in1, w, y0, y1);
+          gsum = gsum + ((c ? y1 - y0 : y0 - y1) - dx);
+        }
+        const double cA = level(a, j / a.L), cB = level(a, j % a.L);
+        const double V = kappa * (cA * cA + cB * cB) - gsum / (double)M;
+        if (V < bv) {
+          sv = bv;
+          bv = V;
+          bj = j;
+        } else if (V == bv) {
+          sv = V;
+          if (tie_wins(j, bj, k, t, s, k0, k1)) bj = j;
+        } else if (V < sv) {
+          sv = V;
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < P; off <<= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const double os = __shfl_xor(sv, off, 64);
+        const uint32_t oj = (uint32_t)__shfl_xor((int)bj, off, 64);
+        const double ns = fmin(fmin(sv, os), fmax(bv, ov));
+        if (ov < bv || (ov == bv && tie_wins(oj, bj, k, t, s, k0, k1))) {
+          bv = ov;
+          bj = oj;
+        }
+        sv = ns;
+      }
+      if (sv > bv && sv - bv < eps) flag = true;
+      // the step itself, with the chosen allocation, on the run's own stream
+      // (allocation 0 if no score compared as a number)
+      const double* d = a.drive + ((uint64_t)(bj == kNone ? 0u : bj) * 9u + stim) * 2u;
+      double y0, y1;
+      lca_step<PREC>(a, x0, x1, d[0], d[1], philox(k, t, s, 0u, k0, k1), y0, y1);
+      x0 = y0;
+      x1 = y1;
+      if (fabs(x0 - th) < eps || fabs(x1 - th) < eps) flag = true;
+      const double mx = x0 > x1 ? x0 : x1;
+      if (mx >= th) {
+        choice = x1 > x0 ? 1 : 0;
+        if (fabs(x0 - x1) < eps) flag = true;
+        break;
+      }
+    }
+    if (j0 == 0) {
+      const uint32_t steps = choice >= 0 ? n : N;
+      uint64_t* st = a.stats + (uint64_t)s * CM_NSTAT;
+      if (choice >= 0) {
+        const uint32_t bin = udiv_magic((steps - 1u) * a.n_bins, a.steps_magic);
+        atomicAdd((unsigned long long*)&a.hist[((uint64_t)s * 2u + choice) * a.n_bins + bin], 1ull);
+        atomicAdd((unsigned long long*)&st[CM_ST_DEC0 + choice], 1ull);
+        atomicAdd((unsigned long long*)&st[CM_ST_SUMN0 + choice], (unsigned long long)steps);
+        atomicAdd((unsigned long long*)&st[CM_ST_SUMSQ0 + choice],
+                  (unsigned long long)steps * (unsigned long long)steps);
+        if (choice == c) atomicAdd((unsigned long long*)&st[CM_ST_CORRECT], 1ull);
+      } else {
+        atomicAdd((unsigned long long*)&st[CM_ST_UNDEC], 1ull);
+      }
+      if (flag) atomicAdd((unsigned long long*)&st[CM_ST_FLAGGED], 1ull);
+      if (a.run_choice) {
+        a.run_choice[run] = (int8_t)choice;
+        a.run_step[run] = steps;
+        a.run_flag[run] = flag ? 1 : 0;
+        if (a.run_state) {
+          a.run_state[run * 2u] = x0;
+          a.run_state[run * 2u + 1u] = x1;
+        }
+      }
+    }
+  }
+}
+
+template <int PREC>
+hipError_t launch_prec(const LoopArgs& a, uint32_t blocks, hipStream_t st) {
+  if (a.J == 1)
+    hipLaunchKernelGGL((loop_kernel<PREC, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+  else if (a.J <= 4)
+    hipLaunchKernelGGL((loop_kernel<PREC, 4>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+  else if (a.J <= 16)
+    hipLaunchKernelGGL((loop_kernel<PREC, 16>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL((loop_kernel<PREC, 64>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t loop_team_lanes(uint32_t J) { return J == 1 ? 1u : J <= 4 ? 4u : J <= 16 ? 16u : 64u; }
+
+hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st) {
+  if (blocks < 1) return hipErrorInvalidValue;
+  return precision == CM_FP64 ? launch_prec<CM_FP64>(a, blocks, st)
+                              : launch_prec<CM_FP32_STEP>(a, blocks, st);
+}
+
+}  // namespace cm

@@ -41,8 +41,15 @@ __device__ void write_drive(const DriveArgs& a, uint64_t i) {
   const double* OB = a.weights + 32;
   const uint64_t s = i / 9u;
   const int stim = (int)(i - s * 9u), ia = stim / 3, ib = stim % 3;
-  const double cA = a.n_signals ? a.grid[s * a.n_signals] : 1.0;
-  const double cB = a.n_signals ? a.grid[s * a.n_signals + 1] : 1.0;
+  double cA, cB;
+  if (a.levels) {  // closed loop: allocation s of the level grid
+    const uint32_t L = a.levels, i = (uint32_t)(s / L), k = (uint32_t)(s % L);
+    cA = L == 1 ? a.amax : (a.amax * (double)i) / (double)(L - 1);
+    cB = L == 1 ? a.amax : (a.amax * (double)k) / (double)(L - 1);
+  } else {
+    cA = a.n_signals ? a.grid[s * a.n_signals] : 1.0;
+    cB = a.n_signals ? a.grid[s * a.n_signals + 1] : 1.0;
+  }
   double hA[4], hB[4];
   for (int k = 0; k < 4; ++k) {
     hA[k] = logistic((cA * a.gain) * (WA[k * 3 + ia] + a.bias));
@@ -84,7 +91,7 @@ __global__ void prep_kernel(PrepBatch b) {
     j -= p.n_extra;
     if (p.kind == CM_DDM) {
       p.d.correct[0] = 1;  // the upper boundary is the correct response
-    } else if (j < 9) {
+    } else if (j < 9) {  // conflict network and its closed loop
       write_correct(p.d, (int)j);
     } else {
       write_drive(p.d, j - 9);

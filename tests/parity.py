@@ -55,7 +55,7 @@ def assert_parity(w, g, o, correct, state_rtol=1e-9, state_atol=1e-12, max_flag_
     assert bad.size == 0, (f"{bad.size} unflagged runs differ; first {bad[:5]}: gpu "
                            f"{g['run_choice'][bad[:5]]}/{g['run_step'][bad[:5]]} oracle "
                            f"{o['run_choice'][bad[:5]]}/{o['run_step'][bad[:5]]}")
-    if int(w["kind"]) == 1:
+    if int(w["kind"]) in (1, 3):  # the conflict LCA, open or closed loop
         amp = lca_growth(w) ** o["run_step"][ok].astype(np.float64)
         tol = np.maximum(state_atol, 1e-13 * amp)[:, None] + state_rtol * np.abs(o["run_state"][ok])
         diff = np.abs(g["run_state"][ok] - o["run_state"][ok])

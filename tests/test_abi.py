@@ -124,3 +124,17 @@ def test_null_arguments():
     d = C.c_int(0)
     assert L.cm_poll(None, 1, C.byref(d)) == cm.E_INVALID
     assert L.cm_serve_config(None, 4) == cm.E_INVALID
+
+
+def test_closed_loop_validation():
+    assert cm.validate(W.control_loop()) == cm.OK
+    assert cm.validate(W.control_loop(costs=[0.0, 0.1], precision=W.FP32_STEP)) == cm.OK
+    for bad in (dict(levels=0), dict(levels=1.5), dict(samples=0), dict(samples=5000),
+                dict(levels=4096, samples=64), dict(amax=-1.0), dict(noise=-0.1)):
+        assert cm.validate(W.control_loop(**bad)) == cm.E_INVALID, bad
+    assert cm.validate(W.control_loop(precision=W.BF16_PROJ)) == cm.E_UNSUPPORTED
+    w = W.control_loop(levels=10)
+    assert cm.workspace_bytes(w) >= 100 * 9 * 2 * 8
+    m, s, keep = cm.structs(w, weights_ptr=8)
+    n = C.c_uint64(0)
+    assert cm.lib().cm_unfused_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)) == cm.E_UNSUPPORTED
