@@ -55,9 +55,11 @@ BATCH = 8
 
 # HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
-# valid only for the kernel sources it was measured on.
-TRAFFIC = {"sources_sha256": "15245ae801b864d410c34a6925ac91a5e85ecb3356eaca74c8020d33625415f3",
-           "bytes_per_launch": 4484301}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
+# valid only for the kernel sources and the runs-per-lane it was measured at
+# (the number of workgroup flushes, hence the write traffic, depends on it).
+TRAFFIC = {"sources_sha256": "41ee7115a9332c712b7db5698ecacced3ac90d4d9bbd75db5786eeb6105f0083",
+           "runs_per_lane": 8,
+           "bytes_per_launch": 1884160}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/internal.hpp")
 
@@ -71,6 +73,87 @@ def sources_hash():
     return h.hexdigest()
 
 
+def _side(name):
+    """(workload dict, launch kind) of a named side workload."""
+    from paper_2110_15425_amd import workloads as W
+    f32 = W.FP32_STEP
+    table = {
+        "c0_fp64": (W.ddm(), "launch"),
+        "c0_fp32": (W.ddm(precision=f32), "launch"),
+        "c0x1000_fp64": (W.ddm(trials=10_000_000), "launch"),
+        "c0x1000_fp32": (W.ddm(trials=10_000_000, precision=f32), "launch"),
+        "c1_fp64": (W.conflict(reward=1.0, cost=0.1), "launch"),
+        "c1_fp32": (W.conflict(reward=1.0, cost=0.1, precision=f32), "launch"),
+        "c2_fp32": (W.grid_search(precision=f32), "launch"),
+        "c2_fp64": (W.grid_search(), "launch"),
+        "c3_bf16": (W.rnn(precision=W.BF16_PROJ), "launch"),
+        "c3_fp64": (W.rnn(), "launch"),
+        "density_c0_64drifts": (W.ddm(drifts=[0.3 * (i + 1) / 64 for i in range(64)]), "density"),
+        "timecourse_c1_fp32": (W.conflict(precision=f32), "timecourse"),
+        "loop_l8_m4_fp32": (W.control_loop(trials=20_000, costs=[0.0, 0.003, 0.01, 0.03],
+                                           precision=f32), "launch"),
+        "loop_l100_m1_fp32": (W.control_loop(trials=1000, levels=100, samples=1,
+                                             costs=[0.0, 0.003, 0.01, 0.03], precision=f32),
+                              "launch"),
+        "unfused_c1_fp32": (W.conflict(precision=f32), "unfused"),
+    }
+    return table[name]
+
+
+SIDE_WORKLOADS = ("c0_fp64", "c0_fp32", "c0x1000_fp64", "c0x1000_fp32", "c1_fp64", "c1_fp32",
+                  "c2_fp32", "c2_fp64", "c3_bf16", "c3_fp64", "density_c0_64drifts",
+                  "timecourse_c1_fp32", "loop_l8_m4_fp32", "loop_l100_m1_fp32",
+                  "unfused_c1_fp32")
+
+
+def side_workload(name, steps, warmup):
+    """Time one named workload (default launch shape); returns its JSON dict."""
+    import torch
+
+    from paper_2110_15425_amd import cm
+    w, how = _side(name)
+    h = cm.Handle(0)
+    ds = cm.DeviceSweep(h, w)
+    if how == "density":
+        out = torch.empty((int(w["n_settings"]), 2, int(w["max_steps"])), dtype=torch.float64,
+                          device="cuda")
+        m, s, keep = cm.structs(w, None, ds.grid.data_ptr())
+
+        def launch():
+            cm.check(cm.lib().cm_ddm_density(h.h, cm.C.byref(m), cm.C.byref(s), 1000, 1e-15,
+                                             cm.C.c_void_p(out.data_ptr()),
+                                             cm.C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    elif how == "timecourse":
+        def launch():
+            ds.launch_timecourse(10)
+    elif how == "unfused":
+        def launch():
+            ds.launch_unfused()
+    else:
+        launch = ds.launch
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    line = {"workload": name, "ms_per_step": ms, "steps": steps}
+    if how != "density":
+        rs = cm.run_steps(w, ds.results())
+        line.update(run_steps=rs, run_steps_per_s=rs / (ms / 1e3))
+    if name.startswith("loop_"):
+        from paper_2110_15425_amd import workloads as W
+        p = w["params"]
+        per_step = int(p[W.LOOP_P["levels"]]) ** 2 * int(p[W.LOOP_P["samples"]])
+        line["lookahead_evaluations_per_s"] = line["run_steps"] * per_step / (ms / 1e3)
+    print(f"# {name}: {ms:.4f} ms/step", file=sys.stderr, flush=True)
+    return line
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +165,9 @@ def parse():
                     help="only the headline workload (no rate network, no served mix)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the served-mix arrival window")
+    ap.add_argument("--workload", choices=sorted(SIDE_WORKLOADS), default=None,
+                    help="time one other workload of the path instead (prints its own JSON "
+                         "line; used to profile each kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
@@ -186,6 +272,9 @@ def main():
     import torch
     from paper_2110_15425_amd import cm, workloads as W
 
+    if args.workload:
+        print(json.dumps(side_workload(args.workload, args.steps, args.warmup)), flush=True)
+        return
     if args.calibrate_copy:
         n = 1 << 30
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
@@ -232,7 +321,9 @@ def main():
 
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
-    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == sources_hash() else None
+    traffic = None
+    if TRAFFIC["sources_sha256"] == sources_hash() and tuned["runs_per_lane"] == TRAFFIC["runs_per_lane"]:
+        traffic = TRAFFIC["bytes_per_launch"]
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",
         "value": head["rate"],
@@ -265,6 +356,8 @@ def main():
     }
     if not args.no_extras:
         line["rate_network"] = rate_network(cm, W)
+        line["time_course"] = side_workload("timecourse_c1_fp32", 10, 2)
+        line["closed_loop"] = side_workload("loop_l8_m4_fp32", 5, 1)
         line["serving"] = serving(cm, args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w64)
