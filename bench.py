@@ -49,16 +49,16 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 LANE_OPS_PER_STEP = {"fp32_step": 78, "fp64": 240}
 
 # "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
-# batched launch per benchmark step, so one sweep's tail of long runs overlaps
-# the next sweep's work.
-BATCH = 8
+# batched launch per benchmark step (the most one launch takes), so one
+# sweep's tail of long runs overlaps the next sweep's work.
+BATCH = 12
 
 # HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
 # valid only for the kernel sources and the runs-per-lane it was measured at
 # (the number of workgroup flushes, hence the write traffic, depends on it).
 TRAFFIC = {"sources_sha256": "41ee7115a9332c712b7db5698ecacced3ac90d4d9bbd75db5786eeb6105f0083",
-           "runs_per_lane": 8,
+           "runs_per_lane": 8, "batch": 8,
            "bytes_per_launch": 1884160}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/internal.hpp")
@@ -296,7 +296,7 @@ def main():
     # untimed: choose the FP32 launch shape on this device
     wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
     tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
-                                candidates=[(r, s) for r in (2, 4, 8, 16, 32) for s in (4, 8, 16, 32)])
+                                candidates=[(r, s) for r in (4, 8, 12, 16, 24) for s in (8, 16, 32)])
     h_single = cm.Handle(0)
     autotune.tune(h_single, w32, reps=2,
                   candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
@@ -322,7 +322,8 @@ def main():
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
     traffic = None
-    if TRAFFIC["sources_sha256"] == sources_hash() and tuned["runs_per_lane"] == TRAFFIC["runs_per_lane"]:
+    if (TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH
+            and tuned["runs_per_lane"] == TRAFFIC["runs_per_lane"]):
         traffic = TRAFFIC["bytes_per_launch"]
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",

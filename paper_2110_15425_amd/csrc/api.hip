@@ -387,8 +387,13 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   uint64_t rpl = tune.runs_per_lane;
   uint64_t chunk;
   if (scan) {
-    // one wavefront per run: a workgroup of 4 wavefronts takes 4 runs per round
-    if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, runs / (32ull * h->cu_count)));
+    // One wavefront per run: a workgroup of 4 wavefronts takes 4 runs per
+    // round.  More runs per wavefront lengthen each wavefront's serial chain;
+    // fewer mean more workgroups, each flushing its histogram window with
+    // atomics into the same few global counters.  The two costs balance near
+    // runs per wavefront ~ sqrt(runs / 600) (measured on MI355X: 2 at 2,000
+    // runs, 4 at 10^4, 4-8 at 5x10^4).
+    if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, (uint64_t)llround(sqrt((double)runs / 600.0))));
     chunk = 4u * rpl;
   } else {
     if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, launch_runs / (1024ull * h->cu_count)));
