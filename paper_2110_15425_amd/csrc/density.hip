@@ -10,40 +10,72 @@
 // and the mass absorbed at either bound from cell i is a Gaussian tail.  The
 // first step leaves the exact start point; later steps leave cell centres
 // (midpoint rule, error O(h^2)).  One workgroup per setting keeps the kernel
-// row, the absorption tables and the mass vector in LDS for all steps.
+// row and the mass vectors in LDS for all steps; up to four groups of
+// threads split the source cells of each step and add their partial sums.
 #include "internal.hpp"
 
 namespace cm {
 namespace {
 
-constexpr int kDensBlock = 256;
+constexpr int kOut = 8;       // consecutive output cells per thread
+constexpr int kFPad = 16;     // zero cells in front of the kernel row
+constexpr int kMaxThreads = 1024;
 
 __device__ __forceinline__ double Phi(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
 
-__global__ __launch_bounds__(kDensBlock) void ddm_density_kernel(DensityArgs a) {
+// LDS index of kernel-row entry x (x >= -kFPad).  Threads own 8 consecutive
+// output cells, so within a wavefront their reads of the row are 8 doubles
+// apart; xor-ing bits 0-2 with bits 4-6 spreads every 16 such reads over the
+// 16 eight-byte LDS bank pairs (no conflicts), and maps each aligned block of
+// 128 entries onto itself.
+__device__ __forceinline__ uint32_t fidx(int x) {
+  const uint32_t u = (uint32_t)(x + kFPad);
+  return u ^ ((u >> 4) & 7u);
+}
+
+// Launch geometry, computed on the host: Q thread groups split the source
+// cells of each step, each group has TPQ threads (a multiple of 64 covering
+// the ceil(M/8) output blocks), block = Q * TPQ.
+__global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a) {
   extern __shared__ double sh[];
-  __shared__ double red[2][kDensBlock / 64];
+  __shared__ double red[2][kMaxThreads / 64];
   const uint32_t M = a.cells, tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t Q = a.splits, TPQ = nt / Q, q = tid / TPQ, blk = tid - q * TPQ;
+  const uint32_t nb = (M + kOut - 1) / kOut;
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  double* f = sh;             // [2M - 1] (+4 zero pad), offset k = d - (M - 1)
-  double* up = f + (2 * M + 3);
-  double* lo = up + M;
-  double* m0 = lo + M;
+  const uint32_t fsize = ((2 * M + kFPad + 8 + 127) / 128) * 128;  // see density_lds_bytes
+  double* f = sh;            // kernel row, swizzled, [fsize]
+  double* m0 = f + fsize;    // mass vectors [M]
   double* m1 = m0 + M;
+  double* part = m1 + M;     // partial sums of splits 1..Q-1, [Q-1][M]
   const uint64_t s = blockIdx.x;
   const double drift = a.n_signals ? a.grid[s * a.n_signals] : a.drift;
   const double as = drift * a.dt, b = a.b, th = a.thresh, h = (2.0 * th) / (double)M;
   double* out_lo = a.out + (s * 2u) * a.max_steps;  // choice 0: lower bound
   double* out_up = out_lo + a.max_steps;             // choice 1: upper bound
 
-  for (uint32_t d = tid; d < 2 * M + 3; d += nt) {
-    const double k = (double)((int)d - (int)(M - 1));
-    f[d] = d < 2 * M - 1 ? Phi(((k + 0.5) * h - as) / b) - Phi(((k - 0.5) * h - as) / b) : 0.0;
+  // kernel row: entry x = d + (M - 1) is the mass moving d cells up
+  for (uint32_t u = tid; u < fsize; u += nt) {
+    const int x = (int)u - kFPad;
+    double v = 0.0;
+    if (x >= 0 && x < (int)(2 * M - 1)) {
+      const double k = (double)(x - (int)(M - 1));
+      v = Phi(((k + 0.5) * h - as) / b) - Phi(((k - 0.5) * h - as) / b);
+    }
+    f[fidx(x)] = v;
   }
-  for (uint32_t i = tid; i < M; i += nt) {
+  // absorption tables of the cells this thread owns, tid + r nt (at most 8:
+  // there are at least ceil(M / 8) threads)
+  double upc[kOut], loc[kOut];
+#pragma unroll
+  for (int r = 0; r < kOut; ++r) {
+    const uint32_t i = tid + (uint32_t)r * nt;
+    upc[r] = 0.0;
+    loc[r] = 0.0;
+    if (i >= M) continue;
     const double c = -th + ((double)i + 0.5) * h;
-    up[i] = Phi(-((th - c) - as) / b);
-    lo[i] = Phi(((-th - c) - as) / b);
+    upc[r] = Phi(-((th - c) - as) / b);
+    loc[r] = Phi(((-th - c) - as) / b);
     // first step from the start point, exact
     const double x0 = a.start;
     const double e0 = -th + (double)i * h, e1 = -th + (double)(i + 1) * h;
@@ -55,15 +87,23 @@ __global__ __launch_bounds__(kDensBlock) void ddm_density_kernel(DensityArgs a) 
   }
   __syncthreads();
 
+  // this thread's share of the convolution: output cells jb..jb+7 from the
+  // source cells [i0, i1) of its group
+  const uint32_t jb = blk * kOut, i0 = (q * M) / Q, i1 = ((q + 1) * M) / Q;
+  const bool active = blk < nb;
   double* cur = m0;
   double* nxt = m1;
   uint32_t n = 2;
   for (; n <= a.max_steps; ++n) {
-    // absorbed at step n, and the survivor mass after it
+    // absorbed at step n
     double pu = 0.0, pl = 0.0;
-    for (uint32_t i = tid; i < M; i += nt) {
-      pu = fma(cur[i], up[i], pu);
-      pl = fma(cur[i], lo[i], pl);
+#pragma unroll
+    for (int r = 0; r < kOut; ++r) {
+      const uint32_t i = tid + (uint32_t)r * nt;
+      if (i < M) {
+        pu = fma(cur[i], upc[r], pu);
+        pl = fma(cur[i], loc[r], pl);
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       pu += __shfl_xor(pu, o, 64);
@@ -73,29 +113,33 @@ __global__ __launch_bounds__(kDensBlock) void ddm_density_kernel(DensityArgs a) 
       red[0][wave] = pu;
       red[1][wave] = pl;
     }
-    // new mass: a 1-D convolution of the mass with the kernel row.  Each
-    // thread produces 4 consecutive cells; the 4 kernel values it needs for
-    // source cell i are a window sliding by one per i, so each LDS read of
-    // the kernel row feeds 4 multiply-adds.
-    for (uint32_t jb = 4u * tid; jb < M; jb += 4u * nt) {
-      const double* fw = f + (M - 1) + jb;  // fw[q - i] = f[j - i + M - 1] for j = jb + q
-      double w0 = fw[0], w1 = fw[1], w2 = fw[2], w3 = fw[3];
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (uint32_t i = 0; i < M; ++i) {
+    // survivor mass: a 1-D convolution with the kernel row.  The 8 row
+    // entries a thread needs for source cell i slide by one per i, so each
+    // LDS read of the row feeds 8 multiply-adds; the source mass cur[i] is
+    // the same for the whole wavefront (a broadcast read).
+    double acc[kOut];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) acc[k] = 0.0;
+    if (active) {
+      const int x0 = (int)jb - (int)i0 + (int)(M - 1);  // row entry of (jb, i0)
+      double w[kOut];
+#pragma unroll
+      for (int k = 0; k < kOut; ++k) w[k] = f[fidx(x0 + k)];
+#pragma unroll 4
+      for (uint32_t i = i0; i < i1; ++i) {
         const double c = cur[i];
-        a0 = fma(c, w0, a0);
-        a1 = fma(c, w1, a1);
-        a2 = fma(c, w2, a2);
-        a3 = fma(c, w3, a3);
-        w3 = w2;
-        w2 = w1;
-        w1 = w0;
-        w0 = (i + 1u < M) ? fw[-(int)(i + 1u)] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kOut; ++k) acc[k] = fma(c, w[k], acc[k]);
+#pragma unroll
+        for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
+        w[0] = f[fidx(x0 - (int)(i - i0) - 1)];  // >= -1: a zero pad entry at the end
       }
-      nxt[jb] = a0;
-      if (jb + 1u < M) nxt[jb + 1u] = a1;
-      if (jb + 2u < M) nxt[jb + 2u] = a2;
-      if (jb + 3u < M) nxt[jb + 3u] = a3;
+      if (q > 0) {
+        double* pq = part + (q - 1) * M;
+#pragma unroll
+        for (int k = 0; k < kOut; ++k)
+          if (jb + k < M) pq[jb + k] = acc[k];
+      }
     }
     __syncthreads();
     if (tid == 0) {
@@ -107,11 +151,20 @@ __global__ __launch_bounds__(kDensBlock) void ddm_density_kernel(DensityArgs a) 
       out_up[n - 1] = su;
       out_lo[n - 1] = sl;
     }
+    if (active && q == 0) {
+#pragma unroll
+      for (int k = 0; k < kOut; ++k) {
+        if (jb + k >= M) break;
+        double v = acc[k];
+        for (uint32_t r = 1; r < Q; ++r) v += part[(r - 1) * M + jb + k];
+        nxt[jb + k] = v;
+      }
+    }
+    __syncthreads();
     // survivor mass: stop once it is negligible
     double sv = 0.0;
     for (uint32_t j = tid; j < M; j += nt) sv += nxt[j];
     for (int o = 32; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-    __syncthreads();
     if (lane == 0) red[0][wave] = sv;
     __syncthreads();
     double tot = 0.0;
@@ -130,9 +183,25 @@ __global__ __launch_bounds__(kDensBlock) void ddm_density_kernel(DensityArgs a) 
 
 }  // namespace
 
+// The kernel row holds 2M - 1 entries after kFPad zeros; windows of invalid
+// output cells (beyond M) read up to 8 entries past it, and the swizzle stays
+// inside aligned blocks of 128, so the row is rounded up to whole blocks with
+// that margin.
+size_t density_lds_bytes(uint32_t cells, uint32_t splits) {
+  const size_t fsize = ((2u * (size_t)cells + kFPad + 8 + 127) / 128) * 128;
+  return (fsize + 2u * (size_t)cells + (size_t)(splits - 1) * cells) * sizeof(double);
+}
+
+uint32_t density_threads_per_split(uint32_t cells) {
+  const uint32_t nb = (cells + kOut - 1) / kOut;
+  return ((nb + 63) / 64) * 64;
+}
+
 hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)(2 * a.cells + 3 + 4 * a.cells) * sizeof(double);
-  hipLaunchKernelGGL(ddm_density_kernel, dim3((uint32_t)a.n_settings), dim3(kDensBlock), lds, st, a);
+  const uint32_t tpq = density_threads_per_split(a.cells);
+  if (a.splits < 1 || a.splits * tpq > (uint32_t)kMaxThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ddm_density_kernel, dim3((uint32_t)a.n_settings), dim3(a.splits * tpq),
+                     density_lds_bytes(a.cells, a.splits), st, a);
   return hipGetLastError();
 }
 

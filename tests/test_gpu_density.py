@@ -40,3 +40,15 @@ def test_density_explains_monte_carlo_histogram():
     exp = np.concatenate([pins.binned(dens[0, 0], 100, 3000), pins.binned(dens[0, 1], 100, 3000)])
     obs = np.concatenate([mc["hist"][0, 0], mc["hist"][0, 1]])
     assert pins.chisq_pvalue(obs, exp) > 1e-4
+
+
+@pytest.mark.parametrize("cells", [16, 57, 1300])
+def test_density_cell_count_extremes(cells):
+    """Smallest and largest grids, and one whose row of kernel entries ends
+    just short of a 128-entry block (the shared-memory layout's edge cases)."""
+    w = W.ddm(drifts=[0.1, -0.4], max_steps=400, n_bins=10)
+    out = cm.ddm_density(w, cells=cells)
+    for s, d in enumerate((0.1, -0.4)):
+        lo, up = oracle.ddm_density(d * 0.01, math.sqrt(0.01), 1.0, cells=cells, max_steps=400)
+        np.testing.assert_allclose(out[s, 0], lo, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(out[s, 1], up, rtol=0, atol=1e-12)
