@@ -168,6 +168,9 @@ def parse():
     ap.add_argument("--workload", choices=sorted(SIDE_WORKLOADS), default=None,
                     help="time one other workload of the path instead (prints its own JSON "
                          "line; used to profile each kernel)")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="only time the FP64 CPU oracle on each configuration, one thread and "
+                         "all threads (the CPU columns of the results table)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
@@ -245,6 +248,43 @@ def serving(cm, seconds):
     return summ
 
 
+def oracle_table():
+    """The FP64 CPU oracle on each configuration with one thread and with all of
+    this host's threads, on bounded samples (runs are independent, so the
+    rate of a sample is the rate of the whole sweep)."""
+    import oracle
+
+    from paper_2110_15425_amd import workloads as W
+    threads = len(os.sched_getaffinity(0))
+    cases = [("c0", W.ddm(), W.ddm()),
+             ("c1", W.conflict(), W.conflict(trials=1000)),
+             ("c2", W.grid_search(), W.grid_search(trials=10)),
+             ("c3", W.rnn(), W.rnn(trials=256))]
+    rows = []
+    for name, full, sample in cases:
+        row = {"config": name, "sample_runs": int(sample["n_settings"] * sample["trials"]),
+               "full_runs": int(full["n_settings"] * full["trials"])}
+        for label, n in (("one_thread", 1), ("all_threads", threads)):
+            small = sample
+            if n == 1 and name in ("c3",):
+                small = W.with_(sample, trials=32)
+            t0 = time.perf_counter()
+            rs, reps = 0, 0
+            while reps == 0 or time.perf_counter() - t0 < 1.0:  # at least a second of work
+                out = oracle.run(small, n_threads=n)
+                rs += oracle.run_steps(small, out)
+                reps += 1
+            dt = time.perf_counter() - t0
+            row[label] = {"run_steps_per_s": rs / dt, "seconds": dt, "repeats": reps,
+                          "runs": int(small["n_settings"] * small["trials"])}
+        row["threads"] = threads
+        rows.append(row)
+        print(f"# oracle {name}: 1 thread {row['one_thread']['run_steps_per_s']:.3e}, "
+              f"{threads} threads {row['all_threads']['run_steps_per_s']:.3e} run-steps/s",
+              file=sys.stderr, flush=True)
+    return rows
+
+
 def cpu_baseline(w):
     """The FP64 oracle on this host: the same sweep, all cores."""
     import oracle
@@ -272,6 +312,9 @@ def main():
     import torch
     from paper_2110_15425_amd import cm, workloads as W
 
+    if args.oracle_table:
+        print(json.dumps({"oracle_table": oracle_table()}), flush=True)
+        return
     if args.workload:
         print(json.dumps(side_workload(args.workload, args.steps, args.warmup)), flush=True)
         return
