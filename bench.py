@@ -44,8 +44,13 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Lane-op slots of one run-step of the conflict-network LCA, by mode: the
 # straight-line work the method needs per step (one Philox4x32-10 block, a
 # Box-Muller pair, the two-unit update and threshold tests), counted from the
-# instruction mix of the step body and weighted by issue rate.  Derivation
-# in DESIGN.md ("Roofline accounting").
+# instruction mix of the step body and weighted by issue rate.  FP32 steps:
+# Philox 37 (nine full rounds of two 32x32->64 multiplies and two three-way
+# xors, the first round's constant-word multiply hoisted), Box-Muller 15
+# (four transcendentals at half rate count twice), update 14 (with the
+# float/double conversions of the FP64 accumulators), tests 8.  FP64: the
+# same Philox block, the double-precision Box-Muller of the device math
+# library (log, sincospi, sqrt: most of the 240) and the double update.
 LANE_OPS_PER_STEP = {"fp32_step": 78, "fp64": 240}
 
 # "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
@@ -300,14 +305,16 @@ def cpu_baseline(w):
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "run-timesteps/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} full sweep(s) of the same workload in FP64 "
-                      f"({steps} run-steps, {dt:.2f} s wall)"}
+                      f"({steps} run-steps, {dt:.2f} s wall on {threads} threads, "
+                      f"{dt * threads:.0f} CPU-seconds)"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(runs shard by setting range across GPUs, see DESIGN.md)", file=sys.stderr)
+              "(a sweep would shard by contiguous run ranges, one per GPU, with an "
+              "all-reduce of the integer outputs)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2110_15425_amd import cm, workloads as W

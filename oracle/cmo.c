@@ -22,8 +22,9 @@
  * The paper prints no equations for the mechanisms; the readings used here
  * (Euler-Maruyama noise scaling, >= at threshold, integer-step decision
  * times, linear LCA, the conflict network's logistic drive, the rate
- * network's centred readout, Philox streams, Box-Muller normals) are listed
- * in the design doc together with the pins that check them.
+ * network's centred readout, Philox streams, Box-Muller normals) are stated
+ * where they are used, and the tests pin each part of this file to values
+ * fixed by the mathematics (closed forms, special cases, brute force).
  *
  * Everything is evaluated in the order written, in FP64 unless a precision
  * mode says otherwise, built with -ffp-contract=off so no FMA is formed.

@@ -9,7 +9,8 @@
  * definition (the Distill paper, Sec. 2.2 "Cognitive Model Execution" and its
  * scheduling listing, Sec. 3.3 "Dynamic to Static Data Structure Conversion",
  * Sec. 3.6 "Parallelism and GPU Acceleration", Sec. 4.4 "Clone detection"
- * for the DDM/LCA mechanisms) plus the readings listed in the design doc.
+ * for the DDM/LCA mechanisms) plus readings, stated where they are used,
+ * for what the paper leaves open.
  *
  * All pointers are HOST pointers.  The caller owns every buffer; outputs are
  * fully overwritten (histograms and statistics are zeroed first).
