@@ -123,3 +123,63 @@ def test_coarse_to_fine_search_matches_full_grid():
     sc = cm.run(evalw, handle=h)["score"]
     print("refined", best, sc[0], "full grid", gbest, sc[1], [r["score"] for r in hist])
     assert sc[0] >= sc[1] - 0.02
+
+
+def _capture(fn):
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up outside capture
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+@pytest.mark.parametrize("what", ["batch", "timecourse", "loop", "rate_network"])
+def test_graph_replays_of_every_launch_kind(what):
+    """A captured launch (batched sweeps of two kinds, the time course, the
+    closed loop, the rate network) replayed several times, with other eager
+    work between replays, gives the eager result every time: the library's
+    preparation kernel clears the outputs inside the graph (no memset nodes)."""
+    h = cm.Handle(0)
+    if what == "batch":
+        ws = [W.ddm(trials=700, seed=2, drifts=[0.1, 0.4]), W.grid_search(n=5, trials=40, seed=3),
+              W.ddm(trials=300, seed=4, precision=W.FP32_STEP)]
+        ds = [cm.DeviceSweep(h, w) for w in ws]
+        eager = [cm.run(w, handle=h) for w in ws]
+        g = _capture(lambda: cm.launch_batch(h, ds))
+    elif what == "timecourse":
+        w = W.conflict(trials=300, grid=W.control_grid(3), precision=W.FP32_STEP)
+        ds = [cm.DeviceSweep(h, w)]
+        eager_out, eager_tc = cm.timecourse(w, 7, handle=h)
+        eager = [eager_out]
+        # the output tensor allocated during capture comes from the graph's pool
+        g = _capture(lambda: ds[0].launch_timecourse(7))
+        tc_buf = ds[0].timecourse
+    elif what == "loop":
+        w = W.control_loop(trials=200, levels=4, samples=2, costs=[0.0, 0.02])
+        ds = [cm.DeviceSweep(h, w)]
+        eager = [cm.run(w, handle=h)]
+        g = _capture(ds[0].launch)
+    else:
+        w = W.rnn(trials=512, n_units=64, precision=W.BF16_PROJ)
+        ds = [cm.DeviceSweep(h, w)]
+        eager = [cm.run(w, handle=h)]
+        g = _capture(ds[0].launch)
+    for rep in range(3):
+        other = cm.run(W.ddm(trials=500, seed=10 + rep), handle=h)
+        assert other["stats"][0, :3].sum() == 500
+        for d in ds:
+            d.hist.fill_(-1)
+            d.stats.fill_(-1)
+        if what == "timecourse":
+            tc_buf.fill_(-1)
+        g.replay()
+        for d, e in zip(ds, eager):
+            _same(d.results(), e)
+        if what == "timecourse":
+            assert np.array_equal(tc_buf.cpu().numpy(), eager_tc)
