@@ -295,7 +295,10 @@ struct ProfScope {
     if (h->used == h->events.size()) {
       std::pair<hipEvent_t, hipEvent_t> p{};
       if ((e = hipEventCreate(&p.first)) != hipSuccess) return e;
-      if ((e = hipEventCreate(&p.second)) != hipSuccess) return e;
+      if ((e = hipEventCreate(&p.second)) != hipSuccess) {
+        (void)hipEventDestroy(p.first);
+        return e;
+      }
       h->events.push_back(p);
     }
     ev = &h->events[h->used++];
@@ -328,15 +331,16 @@ bool scan_ddm(const cm_tuning& t, uint64_t runs) {
   return runs <= (1ull << 20);
 }
 
-// Kernel arguments and launch shape of one lane-kernel sweep.
-// launch_runs: runs of every sweep in the same launch (sets the automatic
-// runs per lane, which trades GPU fill against the tail of each chunk).
 // Time course requested with a launch: output [settings][K][6] and the
 // sample spacing (every = 0: none).
 struct TcSpec {
   int64_t* out = nullptr;
   uint32_t every = 0;
 };
+
+// Kernel arguments and launch shape of one lane-kernel sweep.
+// launch_runs: runs of every sweep in the same launch (sets the automatic
+// runs per lane, which trades GPU fill against the tail of each chunk).
 
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
                     const Layout& L, bool scan, uint64_t launch_runs, const TcSpec& tc,
