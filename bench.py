@@ -371,6 +371,10 @@ def main():
 
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
+    # measured ceiling of the same step (random numbers + update, no tests,
+    # refills or reductions) on this device
+    ceil_rate = cm.ceiling(w32, handle=h_plain)
+    kern_rate = head["run_steps"] / (head["kern_ms"] / 1e3)
     traffic = None
     if (TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH
             and tuned["runs_per_lane"] == TRAFFIC["runs_per_lane"]):
@@ -403,7 +407,9 @@ def main():
                      "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": traffic,
                      "kernel": "sim_lane_kernel<LCA<FP32_STEP>>",
                      "kernel_ms": head["kern_ms"],
-                     "lane_ops_per_run_step": LANE_OPS_PER_STEP["fp32_step"]},
+                     "lane_ops_per_run_step": LANE_OPS_PER_STEP["fp32_step"],
+                     "measured_ceiling_run_steps_per_s": ceil_rate,
+                     "frac_of_measured_ceiling": kern_rate / ceil_rate},
     }
     if not args.no_extras:
         line["rate_network"] = rate_network(cm, W)

@@ -304,6 +304,18 @@ cm_status cm_submit(cm_handle *h, uint32_t n, const cm_model *models, const cm_s
                     void *producer_stream, uint64_t *ticket);
 cm_status cm_poll(cm_handle *h, uint64_t ticket, int *done);
 
+/* Measured ceiling of the lane kernels' step: `lanes` lanes (a multiple of
+ * 256) each run `steps` steps of the model's random numbers (one Philox
+ * block per step, per two steps for the DDM, and its Box-Muller pair) and
+ * state update, from the start state, with no threshold tests, refills or
+ * histogram work; out (DEVICE, [lanes] doubles) receives each lane's final
+ * first unit.  steps * lanes / time is the step rate the instruction mix
+ * itself reaches on the device: the empirical roofline against which a
+ * sweep's rate is compared.  Kinds CM_DDM and CM_CONFLICT_LCA, precisions
+ * CM_FP64 and CM_FP32_STEP; only the model's parameters are read. */
+cm_status cm_ceiling(cm_handle *h, const cm_model *model, uint32_t steps, uint64_t lanes,
+                     double *out, void *hip_stream);
+
 /* Kernel timing.  While enabled, every cm_launch brackets its simulation
  * kernel with a pair of HIP events on the launch stream.  cm_profile_read
  * waits for the recorded events, returns the summed kernel time in

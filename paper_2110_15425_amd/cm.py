@@ -28,6 +28,7 @@ EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_s
            "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_launch_timecourse",
            "cm_unfused_workspace_bytes",
            "cm_launch_unfused", "cm_ddm_density", "cm_serve_config", "cm_submit", "cm_poll",
+           "cm_ceiling",
            "cm_profile", "cm_profile_read", "cm_last_error"]
 
 
@@ -101,6 +102,8 @@ def lib():
                                 C.POINTER(Result), C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
                                 C.POINTER(HostResult), C.c_void_p, C.POINTER(C.c_uint64)]
         L.cm_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
+        L.cm_ceiling.argtypes = [C.c_void_p, C.POINTER(Model), C.c_uint32, C.c_uint64, C.c_void_p,
+                                 C.c_void_p]
         L.cm_profile.argtypes = [C.c_void_p, C.c_int]
         L.cm_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.cm_last_error.restype = C.c_char_p
@@ -343,6 +346,36 @@ def poll(handle, ticket):
     d = C.c_int(0)
     check(lib().cm_poll(handle.h, int(ticket), C.byref(d)))
     return bool(d.value)
+
+
+def ceiling(w, steps=1000, lanes=None, reps=3, handle=None):
+    """Measured step-rate ceiling of the model's random numbers and update
+    (cm_ceiling): run-steps per second with every lane busy and no tests,
+    refills or reductions.  lanes defaults to 8 workgroups of 256 per CU."""
+    import torch
+    h = handle or default_handle()
+    dev = torch.device("cuda", h.device)
+    if lanes is None:
+        lanes = 8 * 256 * torch.cuda.get_device_properties(dev).multi_processor_count
+    m, s, keep = structs(w)
+    out = torch.empty(int(lanes), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(h.device)
+
+    def launch():
+        check(lib().cm_ceiling(h.h, C.byref(m), int(steps), int(lanes),
+                               C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+
+    launch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        launch()
+    e1.record(st)
+    torch.cuda.synchronize(h.device)
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    if not torch.isfinite(out).all():
+        raise RuntimeError("ceiling kernel produced a non-finite state")
+    return float(steps) * float(lanes) / sec
 
 
 def ddm_density(w, cells=1000, tol=1e-15, handle=None):

@@ -864,6 +864,40 @@ cm_status cm_launch_timecourse(cm_handle* h, const cm_model* m, const cm_sweep* 
                            (hipStream_t)hip_stream, tc);
 }
 
+cm_status cm_ceiling(cm_handle* h, const cm_model* m, uint32_t steps, uint64_t lanes, double* out,
+                     void* hip_stream) {
+  if (!h || !m || !out) return fail(CM_E_INVALID, "handle, model and out must not be NULL");
+  if (m->abi_version != CM_ABI_VERSION) return fail(CM_E_INVALID, "abi_version mismatch");
+  if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "the ceiling kernel covers the DDM and the conflict LCA");
+  if (m->precision != CM_FP64 && m->precision != CM_FP32_STEP)
+    return fail(CM_E_UNSUPPORTED, "precision must be CM_FP64 or CM_FP32_STEP");
+  const uint32_t need = m->kind == CM_DDM ? CM_DDM_NPARAM : CM_LCA_NPARAM;
+  if (!m->params || m->n_params < need) return fail(CM_E_INVALID, "params missing");
+  if (steps < 1 || steps > 1000000) return fail(CM_E_INVALID, "steps must be in [1, 10^6]");
+  if (lanes < 256 || lanes % 256 || lanes > (1ull << 32))
+    return fail(CM_E_INVALID, "lanes must be a multiple of 256 in [256, 2^32]");
+  if (!aligned(out, 8)) return fail(CM_E_INVALID, "out must be 8-byte aligned");
+  const double* p = m->params;
+  cm::SimArgs a{};
+  a.seed = 1;
+  if (m->kind == CM_DDM) {
+    a.dt = p[CM_DDM_DT];
+    a.drift = p[CM_DDM_DRIFT];
+    a.b = p[CM_DDM_NOISE] * sqrt(p[CM_DDM_DT]);
+    a.start = p[CM_DDM_START];
+  } else {
+    a.dt = p[CM_LCA_DT];
+    a.leak = p[CM_LCA_LEAK];
+    a.comp = p[CM_LCA_COMP];
+    a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
+  }
+  DeviceGuard guard(h->device);
+  const hipError_t e = cm::launch_ceiling((int)m->kind, (int)m->precision, a, steps, lanes, out,
+                                          (hipStream_t)hip_stream);
+  return e == hipSuccess ? ok() : hip_fail(e, "ceiling kernel");
+}
+
 cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
                           const cm_result* results, void* const* workspaces,
                           const uint64_t* workspace_bytes, void* hip_stream) {

@@ -184,6 +184,8 @@ struct DensityArgs {
 hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const LaneBatch& b,
                            size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
+hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
+                          double* out, hipStream_t st);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 uint32_t loop_team_lanes(uint32_t J);
 hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st);

@@ -231,6 +231,32 @@ struct DDM {
   }
 
   __device__ __forceinline__ void state(double* out) const { out[0] = x; }
+
+  // Ceiling measurement: the random numbers and updates of `steps` steps
+  // (rounded up to pairs) with no tests, exits or bookkeeping.
+  __device__ __forceinline__ void free_init(const SimArgs& A) {
+    a_step = A.drift * A.dt;
+    x = A.start;
+  }
+  __device__ __forceinline__ void free_steps(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                             uint32_t steps) {
+    const float af = (float)a_step, bf = (float)A.b;
+    for (uint32_t p = 0; p < (steps + 1u) / 2u; ++p) {
+      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
+      if (PREC == CM_FP64) {
+        double z0, z1;
+        normals64(w, z0, z1);
+        x = (x + a_step) + A.b * z0;
+        x = (x + a_step) + A.b * z1;
+      } else {
+        float f0, f1;
+        normals32(w, f0, f1);
+        x = x + (double)fmaf(bf, f0, af);
+        x = x + (double)fmaf(bf, f1, af);
+      }
+      L.n += 2;
+    }
+  }
 };
 
 // Two-unit leaky competing accumulator with simultaneous update:
@@ -299,6 +325,39 @@ struct LCA {
   __device__ __forceinline__ void state(double* out) const {
     out[0] = x0;
     out[1] = x1;
+  }
+
+  // Ceiling measurement: the random numbers and updates of `steps` steps
+  // with no tests, exits or bookkeeping (fixed drive).
+  __device__ __forceinline__ void free_init(const SimArgs&) {
+    in0 = 0.3;
+    in1 = 0.2;
+    x0 = 0.0;
+    x1 = 0.0;
+  }
+  __device__ __forceinline__ void free_steps(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                             uint32_t steps) {
+    for (uint32_t k = 0; k < steps; ++k) {
+      const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
+      if (PREC == CM_FP64) {
+        double z0, z1;
+        normals64(w, z0, z1);
+        const double y0 = (x0 + (((in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
+        const double y1 = (x1 + (((in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
+        x0 = y0;
+        x1 = y1;
+      } else {
+        float z0, z1;
+        normals32(w, z0, z1);
+        const float xf0 = (float)x0, xf1 = (float)x1;
+        const float lf = (float)A.leak, cf = (float)A.comp, df = (float)A.dt, bf = (float)A.b;
+        const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
+        const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
+        x0 = x0 + (double)fmaf(bf, z0, i0 * df);
+        x1 = x1 + (double)fmaf(bf, z1, i1 * df);
+      }
+      L.n += 1;
+    }
   }
 };
 
@@ -488,6 +547,25 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
   }
 }
 
+// The lane kernels' step with everything else taken away: every lane runs
+// `steps` steps of random numbers and updates from the start state and
+// writes its final first unit (so the work cannot be optimised out).  The
+// rate it reaches is the measured ceiling of the step's instruction mix.
+template <class M>
+__global__ __launch_bounds__(kBlock) void ceiling_kernel(SimArgs a, uint32_t steps, double* out) {
+  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Lane L{};
+  L.s = 0;
+  L.t = (uint32_t)g;
+  L.n = 0;
+  M m;
+  m.free_init(a);
+  m.free_steps(a, L, (uint32_t)a.seed, (uint32_t)(a.seed >> 32), steps);
+  double st[M::kWidth];
+  m.state(st);
+  out[g] = st[0];
+}
+
 template <class M>
 hipError_t launch_model(const LaneBatch& b, bool tc, size_t lds, hipStream_t st) {
   if (tc)
@@ -514,6 +592,24 @@ hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const La
                                 : launch_model<DDM<CM_FP32_STEP>>(b, tc, lds_bytes, st);
   return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, lds_bytes, st)
                               : launch_model<LCA<CM_FP32_STEP>>(b, tc, lds_bytes, st);
+}
+
+hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
+                          double* out, hipStream_t st) {
+  if (lanes % kBlock || lanes / kBlock > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)(lanes / kBlock)), block(kBlock);
+  if (kind == CM_DDM) {
+    if (precision == CM_FP64)
+      hipLaunchKernelGGL((ceiling_kernel<DDM<CM_FP64>>), grid, block, 0, st, a, steps, out);
+    else
+      hipLaunchKernelGGL((ceiling_kernel<DDM<CM_FP32_STEP>>), grid, block, 0, st, a, steps, out);
+  } else {
+    if (precision == CM_FP64)
+      hipLaunchKernelGGL((ceiling_kernel<LCA<CM_FP64>>), grid, block, 0, st, a, steps, out);
+    else
+      hipLaunchKernelGGL((ceiling_kernel<LCA<CM_FP32_STEP>>), grid, block, 0, st, a, steps, out);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace cm

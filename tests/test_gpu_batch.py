@@ -183,3 +183,25 @@ def test_graph_replays_of_every_launch_kind(what):
             _same(d.results(), e)
         if what == "timecourse":
             assert np.array_equal(tc_buf.cpu().numpy(), eager_tc)
+
+
+@pytest.mark.parametrize("kind", ["ddm", "lca"])
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32_STEP])
+def test_measured_ceiling_bounds_the_sweeps(kind, prec):
+    """The ceiling kernel (the step's random numbers and update alone) runs
+    faster per run-step than a whole sweep of the same model and precision."""
+    import time
+    import torch
+    h = cm.Handle(0)
+    w = W.ddm(trials=2_000_000, precision=prec) if kind == "ddm" else \
+        W.conflict(precision=prec)
+    c = cm.ceiling(w, handle=h)
+    ds = cm.DeviceSweep(h, w)
+    ds.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ds.launch()
+    torch.cuda.synchronize()
+    rate = cm.run_steps(w, ds.results()) / (time.perf_counter() - t0)
+    print(f"{kind} prec {prec}: ceiling {c:.3e}, sweep {rate:.3e} run-steps/s")
+    assert c > rate > 0
