@@ -280,7 +280,12 @@ struct LCA {
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int steps, const H& hook) {
     const double th = A.thresh, eps = A.flag_eps, guard = th - 2.0 * eps;
-    for (int k = 0; k < steps; ++k) {
+    // the step cap bounds the loop, so the body needs no cap test
+    const uint32_t lim = min((uint32_t)steps, A.max_steps - L.n);
+    // FP32 steps: the float images of the state, carried from step to step
+    float xf0 = (float)x0, xf1 = (float)x1;
+    const float gf = (float)guard;
+    for (uint32_t k = 0; k < lim; ++k) {
       const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
       double y0, y1;
       if (PREC == CM_FP64) {
@@ -291,7 +296,6 @@ struct LCA {
       } else {
         float z0, z1;
         normals32(w, z0, z1);
-        const float xf0 = (float)x0, xf1 = (float)x1;
         const float lf = (float)A.leak, cf = (float)A.comp, df = (float)A.dt, bf = (float)A.b;
         const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
         const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
@@ -306,18 +310,32 @@ struct LCA {
       x1 = y1;
       L.n += 1;
       hook(L, x0, x1);
-      // one comparison per step; the exact tests run only within 2 eps of
-      // the threshold, where a unit can be within flag distance or across
-      const double mx = x0 > x1 ? x0 : x1;
-      if (__builtin_expect(mx >= guard, 0)) {
+      // cheap comparisons per step; the exact tests run only within 2 eps of
+      // the threshold, where a unit can be within flag distance or across.
+      // FP32 steps compare the float images of the new state (which the next
+      // step needs anyway) with the float image of the guard: rounding is
+      // monotone, so x >= guard implies float(x) >= float(guard).
+      bool near;
+      if (PREC == CM_FP64) {
+        near = (x0 > x1 ? x0 : x1) >= guard;
+      } else {
+        xf0 = (float)x0;
+        xf1 = (float)x1;
+        near = (xf0 >= gf) | (xf1 >= gf);
+      }
+      if (__builtin_expect(near, 0)) {
         if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+        const double mx = x0 > x1 ? x0 : x1;
         if (mx >= th) {
           L.choice = (x1 > x0) ? 1 : 0;
           if (fabs(x0 - x1) < eps) L.flag = true;
           return false;
         }
       }
-      if (L.n == A.max_steps) { L.choice = -1; return false; }
+    }
+    if (L.n == A.max_steps) {  // the cap, reached without a crossing
+      L.choice = -1;
+      return false;
     }
     return true;
   }
