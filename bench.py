@@ -41,17 +41,17 @@ if ROOT not in sys.path:
 # 64 slots, a quarter-rate one 256).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# Lane-op slots of one run-step of the conflict-network LCA, by mode: the
-# straight-line work the method needs per step (one Philox4x32-10 block, a
-# Box-Muller pair, the two-unit update and threshold tests), counted from the
-# instruction mix of the step body and weighted by issue rate.  FP32 steps:
-# Philox 37 (nine full rounds of two 32x32->64 multiplies and two three-way
-# xors, the first round's constant-word multiply hoisted), Box-Muller 15
-# (four transcendentals at half rate count twice), update 14 (with the
-# float/double conversions of the FP64 accumulators), tests 8.  FP64: the
-# same Philox block, the double-precision Box-Muller of the device math
-# library (log, sincospi, sqrt: most of the 240) and the double update.
-LANE_OPS_PER_STEP = {"fp32_step": 78, "fp64": 240}
+# Lane-op slots of one run-step of the conflict-network LCA in the FP32-steps
+# mode: the straight-line work the method needs per step, counted from the
+# gfx950 instruction mix of the step body: Philox4x32-10 37 (the first
+# round's constant-word multiply hoisted, the last round only the two low
+# products the float normals use), Box-Muller 13 (two 24-bit uniforms, log,
+# sqrt, sin, cos on the transcendental unit, scaling), the two-unit update 10
+# (three fused multiply-adds per unit, the float-to-double conversions and
+# FP64 accumulations), the near-threshold test 5.  Transcendentals count one
+# slot: the step's random numbers and update alone (cm_ceiling) issue at the
+# full rate of 60 slots per step.
+LANE_OPS_PER_STEP = {"fp32_step": 65}
 
 # "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
 # batched launch per benchmark step (the most one launch takes), so one

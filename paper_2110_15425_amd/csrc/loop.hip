@@ -24,6 +24,7 @@
 // the atomics are negligible.  The allocation drive table [L^2][9][2] is
 // computed once per sweep by the preparation kernel.
 #include "internal.hpp"
+#include "lca_step.hpp"
 #include "rng.hpp"
 
 namespace cm {
@@ -47,12 +48,10 @@ __device__ __forceinline__ void lca_step(const LoopArgs& a, double x0, double x1
   } else {
     float z0, z1;
     normals32(w, z0, z1);
+    const LcaF32 pf = lca_f32(a.leak, a.comp, a.dt, a.b);
     const float xf0 = (float)x0, xf1 = (float)x1;
-    const float lf = (float)a.leak, cf = (float)a.comp, df = (float)a.dt, bf = (float)a.b;
-    const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
-    const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
-    y0 = x0 + (double)fmaf(bf, z0, i0 * df);
-    y1 = x1 + (double)fmaf(bf, z1, i1 * df);
+    y0 = x0 + (double)lca_inc_f32(pf, (float)(in0 * a.dt), xf0, xf1, z0);
+    y1 = x1 + (double)lca_inc_f32(pf, (float)(in1 * a.dt), xf1, xf0, z1);
   }
   if (a.nonneg) {
     if (y0 < 0.0) y0 = 0.0;

@@ -80,8 +80,10 @@ __device__ __forceinline__ void normals64(const Words& w, double& z0, double& z1
 // v_cos_f32 take their argument in revolutions, so the angle 2*pi*u needs no
 // multiply.  rho = sqrt(-2 ln u) = sqrt(-2 ln2 * log2 u).
 __device__ __forceinline__ void normals32(const Words& w, float& z0, float& z1) {
-  const float ua = (float)((w.w1 >> 8) + 1u) * 0x1p-24f;
-  const float ub = (float)((w.w3 >> 8) + 1u) * 0x1p-24f;
+  // ((m >> 8) + 1) 2^-24 as one exact fused multiply-add: (m >> 8) < 2^24 is
+  // exact in float and so is the result
+  const float ua = fmaf((float)(w.w1 >> 8), 0x1p-24f, 0x1p-24f);
+  const float ub = fmaf((float)(w.w3 >> 8), 0x1p-24f, 0x1p-24f);
   const float rho = __builtin_amdgcn_sqrtf(-1.38629436f * __builtin_amdgcn_logf(ua));
   z0 = rho * __builtin_amdgcn_cosf(ub);
   z1 = rho * __builtin_amdgcn_sinf(ub);

@@ -20,6 +20,7 @@
 #include <type_traits>
 
 #include "internal.hpp"
+#include "lca_step.hpp"
 #include "rng.hpp"
 
 namespace cm {
@@ -264,6 +265,7 @@ struct DDM {
 template <int PREC>
 struct LCA {
   double x0, x1, in0, in1;
+  float idt0, idt1;  // FP32 steps: float(I_i dt)
   static constexpr int kWidth = 2;
 
   __device__ __forceinline__ void begin(const SimArgs& A, Lane& L) {
@@ -271,6 +273,8 @@ struct LCA {
     const double* d = A.drive + ((uint64_t)L.s * 9u + stim) * 2u;
     in0 = d[0];
     in1 = d[1];
+    idt0 = (float)(in0 * A.dt);
+    idt1 = (float)(in1 * A.dt);
     x0 = 0.0;
     x1 = 0.0;
     L.target = A.correct[stim];
@@ -285,6 +289,7 @@ struct LCA {
     // FP32 steps: the float images of the state, carried from step to step
     float xf0 = (float)x0, xf1 = (float)x1;
     const float gf = (float)guard;
+    const LcaF32 pf = lca_f32(A.leak, A.comp, A.dt, A.b);
     for (uint32_t k = 0; k < lim; ++k) {
       const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
       double y0, y1;
@@ -296,11 +301,8 @@ struct LCA {
       } else {
         float z0, z1;
         normals32(w, z0, z1);
-        const float lf = (float)A.leak, cf = (float)A.comp, df = (float)A.dt, bf = (float)A.b;
-        const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
-        const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
-        y0 = x0 + (double)fmaf(bf, z0, i0 * df);
-        y1 = x1 + (double)fmaf(bf, z1, i1 * df);
+        y0 = x0 + (double)lca_inc_f32(pf, idt0, xf0, xf1, z0);
+        y1 = x1 + (double)lca_inc_f32(pf, idt1, xf1, xf0, z1);
       }
       if (A.nonneg) {
         if (y0 < 0.0) y0 = 0.0;
@@ -347,9 +349,11 @@ struct LCA {
 
   // Ceiling measurement: the random numbers and updates of `steps` steps
   // with no tests, exits or bookkeeping (fixed drive).
-  __device__ __forceinline__ void free_init(const SimArgs&) {
+  __device__ __forceinline__ void free_init(const SimArgs& A) {
     in0 = 0.3;
     in1 = 0.2;
+    idt0 = (float)(in0 * A.dt);
+    idt1 = (float)(in1 * A.dt);
     x0 = 0.0;
     x1 = 0.0;
   }
@@ -367,12 +371,10 @@ struct LCA {
       } else {
         float z0, z1;
         normals32(w, z0, z1);
+        const LcaF32 pf = lca_f32(A.leak, A.comp, A.dt, A.b);
         const float xf0 = (float)x0, xf1 = (float)x1;
-        const float lf = (float)A.leak, cf = (float)A.comp, df = (float)A.dt, bf = (float)A.b;
-        const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)in0));
-        const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)in1));
-        x0 = x0 + (double)fmaf(bf, z0, i0 * df);
-        x1 = x1 + (double)fmaf(bf, z1, i1 * df);
+        x0 = x0 + (double)lca_inc_f32(pf, idt0, xf0, xf1, z0);
+        x1 = x1 + (double)lca_inc_f32(pf, idt1, xf1, xf0, z1);
       }
       L.n += 1;
     }

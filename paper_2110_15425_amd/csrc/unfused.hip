@@ -10,6 +10,7 @@
 // fused kernels compute (same operations in the same order, so identical
 // results); only the execution structure differs.
 #include "internal.hpp"
+#include "lca_step.hpp"
 #include "rng.hpp"
 
 namespace cm {
@@ -102,12 +103,10 @@ __global__ void uf_update_kernel(UnfusedArgs a, int cur) {
         y0 = (x[0] + (((d[0] - a.leak * x[0]) - a.comp * x[1]) * a.dt)) + a.b * z[0];
         y1 = (x[1] + (((d[1] - a.leak * x[1]) - a.comp * x[0]) * a.dt)) + a.b * z[1];
       } else {
-        const float lf = (float)a.leak, cf = (float)a.comp, df = (float)a.dt, bf = (float)a.b;
+        const LcaF32 pf = lca_f32(a.leak, a.comp, a.dt, a.b);
         const float xf0 = (float)x[0], xf1 = (float)x[1];
-        const float i0 = fmaf(-cf, xf1, fmaf(-lf, xf0, (float)d[0]));
-        const float i1 = fmaf(-cf, xf0, fmaf(-lf, xf1, (float)d[1]));
-        y0 = x[0] + (double)fmaf(bf, (float)z[0], i0 * df);
-        y1 = x[1] + (double)fmaf(bf, (float)z[1], i1 * df);
+        y0 = x[0] + (double)lca_inc_f32(pf, (float)(d[0] * a.dt), xf0, xf1, (float)z[0]);
+        y1 = x[1] + (double)lca_inc_f32(pf, (float)(d[1] * a.dt), xf1, xf0, (float)z[1]);
       }
       if (a.nonneg) {
         if (y0 < 0.0) y0 = 0.0;
