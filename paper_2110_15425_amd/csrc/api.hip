@@ -423,6 +423,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   a.window = direct ? 0 : (uint32_t)std::min<uint64_t>((chunk - 1) / T + 2, S);
   groups = (runs + chunk - 1) / chunk;
   lds = direct ? 0 : (size_t)a.window * rec_bytes;
+  if (!scan && !tc.every) lds += cm::lane_stage_bytes((int)m->kind, (int)m->precision);
   return ok();
 }
 

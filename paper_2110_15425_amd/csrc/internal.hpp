@@ -186,6 +186,9 @@ hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const La
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
                           double* out, hipStream_t st);
+// LDS after the histogram window that the lane kernel (without time course)
+// uses to pack unfinished runs while a chunk drains.
+size_t lane_stage_bytes(int kind, int precision);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 uint32_t loop_team_lanes(uint32_t J);
 hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st);

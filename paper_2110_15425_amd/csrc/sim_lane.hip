@@ -13,7 +13,9 @@
 // Scheduling: a workgroup owns a contiguous chunk of runs (setting-major).
 // Lanes claim runs from an LDS counter; a lane whose run ended takes the next
 // one at the following refill point, so waves stay dense while run lengths
-// vary by orders of magnitude.  Finished runs are counted into an LDS
+// vary by orders of magnitude.  Once the chunk's queue is empty the
+// workgroup drains: it repeatedly packs its unfinished runs into the first
+// wavefronts so that the others stop issuing.  Finished runs are counted into an LDS
 // histogram covering the few settings the chunk spans and flushed with one
 // global 64-bit atomic per nonzero bin when the chunk is done.  All
 // reductions are integer additions: results do not depend on the schedule.
@@ -27,6 +29,7 @@ namespace cm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kDrainSteps = 16;  // steps between packings once a chunk's queue is empty
 
 struct Lane {
   uint32_t s, t;   // setting, trial
@@ -423,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   Lane L;
   uint32_t off = threadIdx.x;
   bool have = off < len;
+  __shared__ uint32_t drain_cnt[kBlock / 64];
   auto setup = [&](uint32_t o) {
     const uint32_t local = t_lo + o;  // < 2^31 + chunk
     L.s = s_lo + udiv_magic(local, a.trials_magic);
@@ -435,21 +439,79 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   };
   if (have) setup(off);
 
-  while (__any(have)) {
-    bool running = have;
-    if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
-    if (have && !running) {
-      double st[M::kWidth];
-      m.state(st);
-      record(a, lds, s_lo, L, st, M::kWidth);
-      off = atomicAdd(&next, 1u);
-      have = off < len;
-      if (have) setup(off);
+  auto finish = [&]() {
+    double st[M::kWidth];
+    m.state(st);
+    record(a, lds, s_lo, L, st, M::kWidth);
+  };
+  if constexpr (TC) {
+    while (__any(have)) {
+      bool running = have;
+      if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
+      if (have && !running) {
+        finish();
+        off = atomicAdd(&next, 1u);
+        have = off < len;
+        if (have) setup(off);
+      }
     }
-  }
-  if (!a.direct) {
-    __syncthreads();
-    flush(a, lds, s_lo);
+    if (!a.direct) {
+      __syncthreads();
+      flush(a, lds, s_lo);
+    }
+  } else {
+    // Refill from the chunk's queue while it lasts.
+    for (;;) {
+      if (*(volatile uint32_t*)&next >= len) break;  // one LDS word, the same for the wave
+      bool running = have;
+      if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
+      if (have && !running) {
+        finish();
+        off = atomicAdd(&next, 1u);
+        have = off < len;
+        if (have) setup(off);
+      }
+    }
+    // Drain: every kDrainSteps steps the workgroup packs its unfinished runs
+    // into the first wavefronts (through LDS); the wavefronts beyond the
+    // packed list wait at the barriers without issuing vector work, which
+    // leaves their issue slots to the other workgroups on the compute unit
+    // instead of stepping a few live lanes each.
+    M* stage_m = (M*)(lds + a.window * rec_words(a.n_bins));
+    Lane* stage_l = (Lane*)(stage_m + kBlock);
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (;;) {
+      __syncthreads();  // the stage's previous contents are consumed
+      const uint64_t act = __ballot(have);
+      if (lane == 0) drain_cnt[w] = (uint32_t)__popcll(act);
+      __syncthreads();
+      uint32_t base = 0, total = 0;
+      for (uint32_t v = 0; v < kBlock / 64; ++v) {
+        if (v < w) base += drain_cnt[v];
+        total += drain_cnt[v];
+      }
+      if (have) {
+        const uint32_t i = base + (uint32_t)__popcll(act & below);
+        stage_m[i] = m;
+        stage_l[i] = L;
+      }
+      __syncthreads();
+      if (total == 0) break;  // every run of the chunk is recorded
+      const uint32_t i = w * 64u + lane;
+      have = i < total;
+      if (have) {
+        m = stage_m[i];
+        L = stage_l[i];
+      }
+      bool running = have;
+      if (__any(running)) running = running && m.advance(a, L, k0, k1, kDrainSteps, hook);
+      if (have && !running) {
+        finish();
+        have = false;
+      }
+    }
+    if (!a.direct) flush(a, lds, s_lo);  // the last barrier follows every record
   }
 }
 
@@ -612,6 +674,13 @@ hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const La
                                 : launch_model<DDM<CM_FP32_STEP>>(b, tc, lds_bytes, st);
   return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, lds_bytes, st)
                               : launch_model<LCA<CM_FP32_STEP>>(b, tc, lds_bytes, st);
+}
+
+size_t lane_stage_bytes(int kind, int precision) {
+  size_t m;
+  if (kind == CM_DDM) m = precision == CM_FP64 ? sizeof(DDM<CM_FP64>) : sizeof(DDM<CM_FP32_STEP>);
+  else m = precision == CM_FP64 ? sizeof(LCA<CM_FP64>) : sizeof(LCA<CM_FP32_STEP>);
+  return (size_t)kBlock * (m + sizeof(Lane));
 }
 
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
