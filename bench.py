@@ -66,7 +66,7 @@ TRAFFIC = {"sources_sha256": "41ee7115a9332c712b7db5698ecacced3ac90d4d9bbd75db57
            "runs_per_lane": 8, "batch": 8,
            "bytes_per_launch": 1884160}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
-                  "paper_2110_15425_amd/csrc/internal.hpp")
+                  "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
 
 
 def sources_hash():
@@ -346,10 +346,10 @@ def main():
     # untimed: choose the FP32 launch shape on this device
     wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
     tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
-                                candidates=[(r, s) for r in (4, 8, 12, 16, 24) for s in (8, 16, 32)])
+                                candidates=[(r, s) for r in (4, 6, 8, 12, 16) for s in (8, 12, 16, 32)])
     h_single = cm.Handle(0)
     autotune.tune(h_single, w32, reps=2,
-                  candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 16, 32)])
+                  candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 12, 16, 32)])
     res = {}
     for name, w, h in (("fp32_single", w32, h_single), ("fp64", w64, h_plain)):
         ds = cm.DeviceSweep(h, w)

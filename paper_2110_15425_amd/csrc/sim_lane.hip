@@ -40,6 +40,14 @@ struct Lane {
   uint32_t next_sample;  // time-course variant: next sample step
 };
 
+// A lane's bookkeeping as it is staged through LDS while a workgroup drains
+// (whole words only, so that the copy moves no padding bytes).
+struct LaneWords {
+  uint32_t s, t, n;
+  int32_t target, choice;
+  uint32_t flag;
+};
+
 // Time-course sums.  A sample adds the count and the fixed-point values
 // q(v) = round-half-even(v 2^32) (clamped to +-2^62) of x0, x1, x0^2, x1^2
 // and comp (x0 x1), with two's-complement 64-bit sums: integer additions, so
@@ -206,8 +214,10 @@ struct DDM {
     else x = x + (double)fmaf(bf, zf, af);
     L.n += 1;
     hook(L, x, 0.0);
-    // one comparison per step; the exact tests run only within 2 eps of a bound
-    if (__builtin_expect(fabs(x) >= guard, 0)) {
+    // one comparison per step; the exact tests run only within 2 eps of a
+    // bound (the whole wavefront takes the branch when any lane is near; the
+    // exact tests are false for the others)
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(fabs(x) >= guard) != 0, 0)) {
       const double th = A.thresh;
       if (near_th(x, th, A.flag_eps) || near_th(x, -th, A.flag_eps)) L.flag = true;
       if (x >= th) { L.choice = 1; return false; }
@@ -319,7 +329,9 @@ struct LCA {
       // the threshold, where a unit can be within flag distance or across.
       // FP32 steps compare the float images of the new state (which the next
       // step needs anyway) with the float image of the guard: rounding is
-      // monotone, so x >= guard implies float(x) >= float(guard).
+      // monotone, so x >= guard implies float(x) >= float(guard).  The whole
+      // wavefront takes the branch when any lane is near (the exact tests
+      // are false for the others), so the test needs no per-lane mask.
       bool near;
       if (PREC == CM_FP64) {
         near = (x0 > x1 ? x0 : x1) >= guard;
@@ -328,7 +340,7 @@ struct LCA {
         xf1 = (float)x1;
         near = (xf0 >= gf) | (xf1 >= gf);
       }
-      if (__builtin_expect(near, 0)) {
+      if (__builtin_expect(__builtin_amdgcn_ballot_w64(near) != 0, 0)) {
         if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
         const double mx = x0 > x1 ? x0 : x1;
         if (mx >= th) {
@@ -462,7 +474,8 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   } else {
     // Refill from the chunk's queue while it lasts.
     for (;;) {
-      if (*(volatile uint32_t*)&next >= len) break;  // one LDS word, the same for the wave
+      // one LDS word, the same for the whole wavefront
+      if (__hip_atomic_load(&next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= len) break;
       bool running = have;
       if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
       if (have && !running) {
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
     // leaves their issue slots to the other workgroups on the compute unit
     // instead of stepping a few live lanes each.
     M* stage_m = (M*)(lds + a.window * rec_words(a.n_bins));
-    Lane* stage_l = (Lane*)(stage_m + kBlock);
+    LaneWords* stage_l = (LaneWords*)(stage_m + kBlock);
     const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint64_t below = (1ull << lane) - 1ull;
     for (;;) {
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
       if (have) {
         const uint32_t i = base + (uint32_t)__popcll(act & below);
         stage_m[i] = m;
-        stage_l[i] = L;
+        stage_l[i] = LaneWords{L.s, L.t, L.n, L.target, L.choice, L.flag ? 1u : 0u};
       }
       __syncthreads();
       if (total == 0) break;  // every run of the chunk is recorded
@@ -502,7 +515,13 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
       have = i < total;
       if (have) {
         m = stage_m[i];
-        L = stage_l[i];
+        const LaneWords lw = stage_l[i];
+        L.s = lw.s;
+        L.t = lw.t;
+        L.n = lw.n;
+        L.target = lw.target;
+        L.choice = lw.choice;
+        L.flag = lw.flag != 0u;
       }
       bool running = have;
       if (__any(running)) running = running && m.advance(a, L, k0, k1, kDrainSteps, hook);
@@ -680,7 +699,7 @@ size_t lane_stage_bytes(int kind, int precision) {
   size_t m;
   if (kind == CM_DDM) m = precision == CM_FP64 ? sizeof(DDM<CM_FP64>) : sizeof(DDM<CM_FP32_STEP>);
   else m = precision == CM_FP64 ? sizeof(LCA<CM_FP64>) : sizeof(LCA<CM_FP32_STEP>);
-  return (size_t)kBlock * (m + sizeof(Lane));
+  return (size_t)kBlock * (m + sizeof(LaneWords));
 }
 
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,

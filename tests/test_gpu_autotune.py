@@ -1,0 +1,53 @@
+"""The autotuner on the device: it installs the shape it reports, the shape
+leaves integer results unchanged, and the JSON cache is reused without
+re-timing."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2110_15425_amd import autotune, cm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CANDS = [(2, 8), (4, 16), (8, 4)]
+
+
+def test_tune_installs_the_fastest_listed_shape():
+    h = cm.Handle(0)
+    w = W.conflict(trials=400, precision=W.FP32_STEP)
+    before = cm.run(w, handle=h)
+    t, ms, table = autotune.tune(h, w, reps=2, candidates=CANDS, finalists=2, rounds=2)
+    assert len(table) == len(CANDS)
+    assert {(r[0], r[1]) for r in table} == set(CANDS)
+    best = min(table, key=lambda r: r[3])
+    assert (t["runs_per_lane"], t["steps_per_sync"]) == (best[0], best[1])
+    assert ms == best[3] > 0
+    assert h.get_tuning(W.LCA, W.FP32_STEP) == t
+    after = cm.run(w, handle=h)
+    for k in ("hist", "stats"):
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_tune_a_batch():
+    h = cm.Handle(0)
+    ws = [W.ddm(trials=5000, seed=s, precision=W.FP32_STEP) for s in (1, 2, 3)]
+    t, ms, table = autotune.tune(h, ws, reps=2, candidates=[(2, 8), (4, 8, 64)], finalists=1,
+                                 rounds=1)
+    assert (t["runs_per_lane"], t["steps_per_sync"], t["lanes_per_run"]) in \
+        {(2, 8, 1), (4, 8, 64)}
+    assert ms > 0
+
+
+def test_tuned_handle_cache_round_trip(tmp_path):
+    path = tmp_path / "tune.json"
+    w = W.conflict(trials=300)
+    h1, t1, table1 = autotune.tuned_handle(w, cache_path=str(path), reps=1, candidates=CANDS,
+                                           finalists=1, rounds=1)
+    assert table1 is not None  # timed
+    cache = json.loads(path.read_text())
+    assert list(cache.values()) == [t1]
+    h2, t2, table2 = autotune.tuned_handle(w, cache_path=str(path), reps=1, candidates=CANDS)
+    assert table2 is None  # from the cache
+    assert t2 == t1
+    assert h2.get_tuning(W.LCA, W.FP64) == t1
