@@ -48,10 +48,12 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # products the float normals use), Box-Muller 13 (two 24-bit uniforms, log,
 # sqrt, sin, cos on the transcendental unit, scaling), the two-unit update 10
 # (three fused multiply-adds per unit, the float-to-double conversions and
-# FP64 accumulations), the near-threshold test 5.  Transcendentals count one
-# slot: the step's random numbers and update alone (cm_ceiling) issue at the
-# full rate of 60 slots per step.
-LANE_OPS_PER_STEP = {"fp32_step": 65}
+# FP64 accumulations), the near-threshold test 4 (the float images of the new
+# state, which the next step needs anyway, a max and one compare; whether any
+# lane is near is a scalar test).  Transcendentals count one slot: the step's
+# random numbers and update alone (cm_ceiling) issue at the full rate of 60
+# slots per step.
+LANE_OPS_PER_STEP = {"fp32_step": 64}
 
 # "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
 # batched launch per benchmark step (the most one launch takes), so one
@@ -60,11 +62,13 @@ BATCH = 12
 
 # HBM traffic of the simulation kernel from the profiler (FETCH_SIZE,
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain 1 GiB copy),
-# valid only for the kernel sources and the runs-per-lane it was measured at
-# (the number of workgroup flushes, hence the write traffic, depends on it).
-TRAFFIC = {"sources_sha256": "41ee7115a9332c712b7db5698ecacced3ac90d4d9bbd75db5786eeb6105f0083",
-           "runs_per_lane": 8, "batch": 8,
-           "bytes_per_launch": 1884160}  # profiles/sim_lane_lca_fp32_conflict_batch8.md
+# valid only for the kernel sources it was measured on, and given per
+# runs-per-lane (the number of workgroup flushes, hence the write traffic,
+# depends on it).
+TRAFFIC = {"sources_sha256": "c350d261b59625ecfc3cba55971b2ca960ddb538f656b5990042b7ef638cf5ba",
+           "batch": 12,
+           # profiles/sim_lane_lca_fp32_conflict_batched.md
+           "bytes_per_launch": {6: 3314533, 8: 2825062}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
 
@@ -179,6 +183,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--shape", default=None, metavar="RPL,SPS",
+                    help="use this runs_per_lane,steps_per_sync for the batched launch instead "
+                         "of tuning it (so that separate profiler runs see the same shape)")
     return ap.parse_args()
 
 
@@ -345,8 +352,14 @@ def main():
     h_tuned = cm.Handle(0)
     # untimed: choose the FP32 launch shape on this device
     wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
-    tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
-                                candidates=[(r, s) for r in (4, 6, 8, 12, 16) for s in (8, 12, 16, 32)])
+    if args.shape:
+        rpl, sps = (int(v) for v in args.shape.split(","))
+        h_tuned.set_tuning(W.LCA, W.FP32_STEP, runs_per_lane=rpl, steps_per_sync=sps)
+        tuned = h_tuned.get_tuning(W.LCA, W.FP32_STEP)
+    else:
+        tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
+                                    candidates=[(r, s) for r in (4, 6, 8, 12, 16)
+                                                for s in (8, 12, 16, 32)])
     h_single = cm.Handle(0)
     autotune.tune(h_single, w32, reps=2,
                   candidates=[(r, s) for r in (1, 2, 4) for s in (4, 8, 12, 16, 32)])
@@ -376,9 +389,8 @@ def main():
     ceil_rate = cm.ceiling(w32, handle=h_plain)
     kern_rate = head["run_steps"] / (head["kern_ms"] / 1e3)
     traffic = None
-    if (TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH
-            and tuned["runs_per_lane"] == TRAFFIC["runs_per_lane"]):
-        traffic = TRAFFIC["bytes_per_launch"]
+    if TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH:
+        traffic = TRAFFIC["bytes_per_launch"].get(tuned["runs_per_lane"])
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",
         "value": head["rate"],

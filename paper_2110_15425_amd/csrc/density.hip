@@ -10,7 +10,7 @@
 // and the mass absorbed at either bound from cell i is a Gaussian tail.  The
 // first step leaves the exact start point; later steps leave cell centres
 // (midpoint rule, error O(h^2)).  One workgroup per setting keeps the kernel
-// row and the mass vectors in LDS for all steps; up to four groups of
+// row and the mass vectors in LDS for all steps; up to eight groups of
 // threads split the source cells of each step and add their partial sums.
 #include "internal.hpp"
 
