@@ -223,16 +223,19 @@ struct DDM {
       if (x >= th) { L.choice = 1; return false; }
       if (x <= -th) { L.choice = 0; return false; }
     }
-    if (L.n == A.max_steps) { L.choice = -1; return false; }
     return true;
   }
 
+  // A running lane enters at an even step count (runs start at 0 and take
+  // whole pairs until they end), so the pairs that end at or before the cap
+  // need no cap test; an odd cap leaves one single step.
   template <class H>
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int pairs, const H& hook) {
     const float af = (float)a_step, bf = (float)A.b;
     const double guard = A.thresh - 2.0 * A.flag_eps;
-    for (int p = 0; p < pairs; ++p) {
+    const uint32_t full = min((uint32_t)pairs, (A.max_steps - L.n) >> 1);
+    for (uint32_t p = 0; p < full; ++p) {
       const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
       double z0 = 0, z1 = 0;
       float f0 = 0, f1 = 0;
@@ -240,6 +243,18 @@ struct DDM {
       else normals32(w, f0, f1);
       if (!one(A, L, z0, f0, af, bf, guard, hook)) return false;
       if (!one(A, L, z1, f1, af, bf, guard, hook)) return false;
+    }
+    if (full < (uint32_t)pairs && L.n < A.max_steps) {  // the cap's own step, first of a pair
+      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
+      double z0 = 0, z1 = 0;
+      float f0 = 0, f1 = 0;
+      if (PREC == CM_FP64) normals64(w, z0, z1);
+      else normals32(w, f0, f1);
+      if (!one(A, L, z0, f0, af, bf, guard, hook)) return false;
+    }
+    if (L.n == A.max_steps) {  // the cap, reached without a crossing
+      L.choice = -1;
+      return false;
     }
     return true;
   }

@@ -53,6 +53,31 @@ def test_batch_larger_than_one_launch():
         _same(d.results(), a)
 
 
+@pytest.mark.parametrize("rpl,sps", [(6, 12), (8, 16)])
+def test_benchmark_batched_launch(rpl, sps):
+    """The benchmark's timed launch: twelve C1 sweeps (noise seeds 1..12) in
+    FP32 steps as one batched launch at a shape the autotuner picks there;
+    each sweep's integers equal the same sweep launched alone at the default
+    shape, and the first is within the FP32 accuracy bound of the FP64
+    oracle on its paired streams."""
+    import oracle
+    from parity import hist_l1
+
+    w32 = W.with_(W.conflict(reward=1.0, cost=0.1), precision=W.FP32_STEP)
+    ws = [W.with_(w32, seed=1 + i) for i in range(12)]
+    print(f"case benchmark batch x12 rpl={rpl} sps={sps}", flush=True)
+    h = cm.Handle(0)
+    h.set_tuning(W.LCA, W.FP32_STEP, runs_per_lane=rpl, steps_per_sync=sps)
+    ds = [cm.DeviceSweep(h, w) for w in ws]
+    cm.launch_batch(h, ds)
+    got = [d.results() for d in ds]
+    h0 = cm.Handle(0)
+    for w, g in zip(ws, got):
+        _same(g, cm.run(w, handle=h0))
+    o64 = oracle.run(W.with_(ws[0], precision=W.FP64))
+    assert hist_l1(got[0], o64, int(w32["trials"])).max() < 0.02
+
+
 def test_batch_rejects_whole_batch_on_one_bad_entry():
     h = cm.Handle(0)
     good = cm.DeviceSweep(h, W.ddm(trials=10))
