@@ -11,11 +11,11 @@
 //
 // Many runs share W, so the projection of 16 runs is one 16-column matrix
 // product per step.  A workgroup of four wavefronts owns 16 run slots; wave
-// w owns a quarter of the units of all 16 runs.  With the 16x16 MFMA layouts
-// the output rows a lane holds (units 16b + 4g + q of run j, for lane
-// j + 16 g) are exactly the rows it must supply as the B operand of the
-// next step, so each lane updates its own units, evaluates their logistic
-// and publishes them through LDS without any reshuffle.
+// w owns a quarter of the units of all 16 runs.  In the 16x16 MFMA output
+// layout lane j + 16 g holds units 16b + 4g + q (q = 0..3) of run j, so each
+// lane updates its own units, evaluates their logistic and publishes them
+// through LDS in blocks of 16 units; the bf16 product reads them back as the
+// B operand of 16x16x32 MFMAs (two published quads per lane and K block).
 //
 // bf16 path: each wave keeps its quarter of W (bf16, matrix-core fragment
 // order) in registers for the whole kernel; r goes through LDS as bf16 B
@@ -35,6 +35,7 @@ namespace cm {
 namespace {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -121,17 +122,23 @@ __global__ __launch_bounds__(kRnnBlock, 2) void rnn_bf16_kernel(RnnArgs a) {
   constexpr int NBW = NB / 4;  // output blocks per wave
   constexpr int NU = NB * 16;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, j = l & 15, g = l >> 4;
-  __shared__ bf16x4 rt[NB][64];  // B fragments of r for the 16 slots
+  __shared__ bf16x4 rt[NB][64];  // r of the 16 slots: [16-unit block][lane j + 16 g] = 4 units
   __shared__ float ypart[4][2][16];
   __shared__ float Rs[2][NU];
 
   // this wave's quarter of W as A fragments: block b = w NBW + bw, K block kb
-  bf16x4 A[NBW][NB];
-  const bf16x4* wf = (const bf16x4*)a.wfrag;
+  // of 32 units
+  constexpr int NK = NB / 2;
+  bf16x8 A[NBW][NK];
+  const bf16x8* wf = (const bf16x8*)a.wfrag;
 #pragma unroll
   for (int bw = 0; bw < NBW; ++bw)
 #pragma unroll
-    for (int kb = 0; kb < NB; ++kb) A[bw][kb] = wf[((w * NBW + bw) * NB + kb) * 64 + l];
+    for (int kb = 0; kb < NK; ++kb) A[bw][kb] = wf[((w * NBW + bw) * NK + kb) * 64 + l];
+  // B operand of K block kb: units 32 kb + 8 g + 0..7 of run j, i.e. the
+  // quads published by lanes j + 16 (2 (g & 1)) and j + 16 (2 (g & 1) + 1)
+  // for 16-unit block 2 kb + g / 2
+  const int bh = g >> 1, bl = j + 32 * (g & 1);
   for (int i = tid; i < 2 * NU; i += kRnnBlock) Rs[i / NU][i % NU] = (float)a.R[i];
 
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -177,11 +184,12 @@ __global__ __launch_bounds__(kRnnBlock, 2) void rnn_bf16_kernel(RnnArgs a) {
 #pragma unroll
     for (int bw = 0; bw < NBW; ++bw) P[bw] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < NB; ++kb) {
-      const bf16x4 B = rt[kb][l];
+    for (int kb = 0; kb < NK; ++kb) {
+      const bf16x4 lo = rt[2 * kb + bh][bl], hi = rt[2 * kb + bh][bl + 16];
+      const bf16x8 B = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 #pragma unroll
       for (int bw = 0; bw < NBW; ++bw)
-        P[bw] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[bw][kb], B, P[bw], 0, 0, 0);
+        P[bw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[bw][kb], B, P[bw], 0, 0, 0);
     }
     __syncthreads();  // all reads of rt done
 
@@ -387,7 +395,8 @@ __global__ __launch_bounds__(kRnnBlock, 2) void rnn_f64_kernel(RnnArgs a) {
 }
 
 // W (fp64 row-major n x n) -> matrix-core fragment order.
-//  bf16: fragment (b, kb), lane l = i + 16 k4 holds W[16b + i][16kb + 4k4 + 0..3].
+//  bf16: fragment (b, kb) for 16x16x32 MFMAs, lane l = i + 16 k8 holds
+//        W[16b + i][32kb + 8k8 + 0..7].
 //  fp64: fragment (b, kb4 = 4 bb + q), lane l = i + 16 k holds
 //        W[16b + 4 (i % 4) + i / 4][16bb + 4k + q].
 __global__ void rnn_prep_kernel(const double* W, uint32_t n, void* out, int bf16) {
@@ -397,11 +406,11 @@ __global__ void rnn_prep_kernel(const double* W, uint32_t n, void* out, int bf16
        e += (uint64_t)gridDim.x * blockDim.x) {
     if (bf16) {
       // e enumerates (b, kb, lane, item)
-      const uint32_t item = e & 3u, lane = (e >> 2) & 63u;
-      const uint64_t frag = e >> 8;
-      const uint32_t kb = (uint32_t)(frag % NB), b = (uint32_t)(frag / NB);
-      const uint32_t i = lane & 15u, k4 = lane >> 4;
-      const double v = W[(uint64_t)(16u * b + i) * n + 16u * kb + 4u * k4 + item];
+      const uint32_t item = e & 7u, lane = (e >> 3) & 63u, NK = NB / 2u;
+      const uint64_t frag = e >> 9;
+      const uint32_t kb = (uint32_t)(frag % NK), b = (uint32_t)(frag / NK);
+      const uint32_t i = lane & 15u, k8 = lane >> 4;
+      const double v = W[(uint64_t)(16u * b + i) * n + 32u * kb + 8u * k8 + item];
       ((__bf16*)out)[e] = (__bf16)(float)v;
     } else {
       // e enumerates (b, kb4, lane).  The fp64 16x16x4 accumulator holds row
