@@ -65,10 +65,10 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "c350d261b59625ecfc3cba55971b2ca960ddb538f656b5990042b7ef638cf5ba",
+TRAFFIC = {"sources_sha256": "595e1c2dafc8c0d080b7e44fb6d47ea71aa18db8be5b28c88b77f25f4530aa54",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md
-           "bytes_per_launch": {6: 3314533, 8: 2825062}}
+           "bytes_per_launch": {6: 3317605, 8: 2828134}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
 
