@@ -134,3 +134,39 @@ def test_fp32_steps_against_fp64_oracle(kind):
         assert g["best"][0] in ks or abs(g["score"].max() - o64["score"].max()) <= 1.0 / T + 1e-12
     else:
         assert l1.max() < 0.02
+
+
+@pytest.mark.parametrize("kind", ["ddm", "lca"])
+def test_large_sweep_sampled(kind):
+    """The largest benchmarked run counts (10^7 DDM trials; 9 x 10^6 LCA runs)
+    in one lane-kernel launch: the histograms and statistics equal the
+    recount of every run's dump, and runs at the ends of the first and last
+    setting and on both sides of workgroup-chunk boundaries match the oracle
+    run by run (choice and decision step exact unless flagged, final state
+    within 1e-9)."""
+    from parity import reduce_dumps
+    if kind == "ddm":
+        w = W.ddm(trials=10_000_000, seed=21)
+    else:
+        w = W.conflict(trials=1_000_000, seed=22, grid=W.control_grid(3))
+    h = cm.Handle(0)
+    h.set_tuning(w["kind"], w["precision"], runs_per_lane=16, steps_per_sync=8, lanes_per_run=1)
+    print(f"case large sweep kind={kind} S={w['n_settings']} T={w['trials']}", flush=True)
+    g = cm.run(w, dumps=True, handle=h)
+    hist, stats = reduce_dumps(w, g, _correct(w))
+    assert np.array_equal(hist, g["hist"]) and np.array_equal(stats, g["stats"])
+    S, T = int(w["n_settings"]), int(w["trials"])
+    chunk = 256 * 16
+    trials = sorted({0, 1, T - 2, T - 1, chunk - 1, chunk, 7 * chunk - 1, 7 * chunk,
+                     (T // chunk) * chunk - 1})
+    checked = 0
+    for s in (0, S - 1):
+        for t in trials:
+            traj, ch, fl = oracle.trajectory(w, s, t)
+            i = s * T + t
+            if fl or g["run_flag"][i]:
+                continue
+            assert g["run_choice"][i] == ch and g["run_step"][i] == traj.shape[0], (s, t)
+            np.testing.assert_allclose(g["run_state"][i], traj[-1], rtol=1e-9, atol=1e-12)
+            checked += 1
+    assert checked >= len(trials)
