@@ -174,9 +174,10 @@ typedef struct {
  * reports the stored values (runs_per_lane 0 = size-dependent).
  *  block          threads per workgroup (64..1024, multiple of 64).
  *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane
- *                 (0: chosen per launch from the sweep size).
+ *                 (0: chosen per launch from the run count, 2..8).
  *  steps_per_sync lane-per-run kernels: steps between refills of finished
- *                 lanes (1..64).
+ *                 lanes (1..64; the DDM counts step pairs).  Defaults: 16
+ *                 steps (LCA), 8 pairs (DDM).
  *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64).
  *  lanes_per_run  DDM only: 1 (one lane per run), 64 (one wavefront per
  *                 run, 128 steps per prefix scan; runs_per_lane then counts

@@ -223,7 +223,7 @@ cm_tuning default_tuning(uint32_t kind, uint32_t prec) {
   cm_tuning t{};
   t.block = 256;
   t.runs_per_lane = 0;
-  t.steps_per_sync = kind == CM_DDM ? 4 : 16;  // DDM counts step pairs
+  t.steps_per_sync = kind == CM_DDM ? 8 : 16;  // DDM counts step pairs
   t.tile_rows = 64;
   t.lanes_per_run = 0;  // DDM: chosen per launch (see plan_lane)
   (void)prec;
@@ -385,9 +385,10 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     a.drive = (const double*)(ws + L.drive);
   }
   // Few runs per lane keep every SIMD busy when the launch is small (the tail
-  // of long runs dominates); many runs per lane amortise the end of each
-  // workgroup's chunk when the launch is large.  Measured on MI355X: 2 for
-  // ~10^5-10^6 runs, 16 for ~10^7.
+  // of long runs dominates); more runs per lane amortise the end of each
+  // workgroup's chunk when the launch is large, until too few workgroups are
+  // left to balance the GPU.  Measured on MI355X: 2 for ~10^5-10^6 runs, 6-8
+  // for ~10^7.
   uint64_t rpl = tune.runs_per_lane;
   uint64_t chunk;
   if (scan) {
@@ -400,7 +401,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, (uint64_t)llround(sqrt((double)runs / 600.0))));
     chunk = 4u * rpl;
   } else {
-    if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(16, launch_runs / (1024ull * h->cu_count)));
+    if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(8, launch_runs / (4096ull * h->cu_count)));
     chunk = (uint64_t)tune.block * rpl;
   }
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
