@@ -31,6 +31,7 @@ namespace cm {
 namespace {
 
 constexpr int kLoopBlock = 256;
+constexpr int kLoopChains = 4;  // allocations a lane of a wide search evaluates together
 constexpr uint32_t kStreamLook = 0x80000000u;  // | (allocation * M + sample)
 constexpr uint32_t kStreamPick = 0xC0000000u;  // | allocation
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -74,7 +75,7 @@ __device__ __forceinline__ bool tie_wins(uint32_t j, uint32_t bj, uint32_t k, ui
   return pj < pb || (pj == pb && j < bj);
 }
 
-template <int PREC, int P>
+template <int PREC, int P, int U>
 __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
   const uint32_t j0 = (threadIdx.x & 63u) % (uint32_t)P;
   const uint32_t teams_per_block = kLoopBlock / P;
@@ -97,27 +98,47 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
       const double dx = c ? x1 - x0 : x0 - x1;  // x_c - x_w
       double bv = INFINITY, sv = INFINITY;
       uint32_t bj = kNone;
-      for (uint32_t j = j0; j < J; j += P) {
-        const double* d = a.drive + ((uint64_t)j * 9u + stim) * 2u;
-        const double in0 = d[0], in1 = d[1];
-        double gsum = 0.0;
-        for (uint32_t m = 0; m < M; ++m) {
-          const Words w = philox(k, t, s, kStreamLook | (j * M + m), k0, k1);
-          double y0, y1;
-          lca_step<PREC>(a, x0, x1, in0, in1, w, y0, y1);
-          gsum = gsum + ((c ? y1 - y0 : y0 - y1) - dx);
+      // A lane's allocations j0, j0 + P, ... are evaluated U at a time, so
+      // that U independent random-number chains are in flight (a wide search
+      // otherwise waits on one chain's latency); they are compared in
+      // allocation order, as one at a time would.  Slots past J repeat
+      // allocation j and are discarded.
+      for (uint32_t j = j0; j < J; j += U * P) {
+        double gs[U], i0[U], i1[U];
+        uint32_t ju[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          ju[u] = j + u * P < J ? j + u * P : j;
+          const double* d = a.drive + ((uint64_t)ju[u] * 9u + stim) * 2u;
+          i0[u] = d[0];
+          i1[u] = d[1];
+          gs[u] = 0.0;
         }
-        const double cA = level(a, j / a.L), cB = level(a, j % a.L);
-        const double V = kappa * (cA * cA + cB * cB) - gsum / (double)M;
-        if (V < bv) {
-          sv = bv;
-          bv = V;
-          bj = j;
-        } else if (V == bv) {
-          sv = V;
-          if (tie_wins(j, bj, k, t, s, k0, k1)) bj = j;
-        } else if (V < sv) {
-          sv = V;
+        for (uint32_t m = 0; m < M; ++m) {
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u) {
+            const Words w = philox(k, t, s, kStreamLook | (ju[u] * M + m), k0, k1);
+            double y0, y1;
+            lca_step<PREC>(a, x0, x1, i0[u], i1[u], w, y0, y1);
+            gs[u] = gs[u] + ((c ? y1 - y0 : y0 - y1) - dx);
+          }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          if (j + u * P >= J) break;
+          const uint32_t jj = ju[u];
+          const double cA = level(a, jj / a.L), cB = level(a, jj % a.L);
+          const double V = kappa * (cA * cA + cB * cB) - gs[u] / (double)M;
+          if (V < bv) {
+            sv = bv;
+            bv = V;
+            bj = jj;
+          } else if (V == bv) {
+            sv = V;
+            if (tie_wins(jj, bj, k, t, s, k0, k1)) bj = jj;
+          } else if (V < sv) {
+            sv = V;
+          }
         }
       }
 #pragma unroll
@@ -179,13 +200,15 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
 template <int PREC>
 hipError_t launch_prec(const LoopArgs& a, uint32_t blocks, hipStream_t st) {
   if (a.J == 1)
-    hipLaunchKernelGGL((loop_kernel<PREC, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+    hipLaunchKernelGGL((loop_kernel<PREC, 1, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
   else if (a.J <= 4)
-    hipLaunchKernelGGL((loop_kernel<PREC, 4>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+    hipLaunchKernelGGL((loop_kernel<PREC, 4, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
   else if (a.J <= 16)
-    hipLaunchKernelGGL((loop_kernel<PREC, 16>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+    hipLaunchKernelGGL((loop_kernel<PREC, 16, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+  else if (a.J < 4u * 64u)  // fewer than four allocations per lane
+    hipLaunchKernelGGL((loop_kernel<PREC, 64, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
   else
-    hipLaunchKernelGGL((loop_kernel<PREC, 64>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
+    hipLaunchKernelGGL((loop_kernel<PREC, 64, kLoopChains>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
   return hipGetLastError();
 }
 

@@ -22,6 +22,11 @@ CASES = {
     "levels8": W.control_loop(trials=450, levels=8, samples=4, costs=[0.0, 0.003, 0.01, 0.3]),
     # more allocations than lanes: lanes stride
     "levels10_stride": W.control_loop(trials=180, levels=10, samples=2, costs=[0.01], seed=7),
+    # wide searches: each lane evaluates four allocations at a time, the last
+    # group ragged (289 = 4 x 64 + 33) or whole (1024 = 4 groups of 4 x 64)
+    "levels17_chains": W.control_loop(trials=120, levels=17, samples=2, costs=[0.0, 0.02],
+                                      seed=8),
+    "levels32_chains": W.control_loop(trials=60, levels=32, samples=1, costs=[0.003], seed=9),
     "no_signals_short_cap": W.control_loop(trials=200, levels=5, samples=2, max_steps=15,
                                            n_bins=5),
     "nonneg": W.control_loop(trials=180, levels=4, samples=2, nonneg=1.0, costs=[0.0, 0.01]),
