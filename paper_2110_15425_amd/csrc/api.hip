@@ -589,13 +589,15 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   a.run_state = r->run_state;
   cm_status st = enqueue_prep(m, s, r, ws, L, stream);
   if (st != CM_OK) return st;
-  const uint64_t teams_per_block = 256u / cm::loop_team_lanes(a.J);
+  const uint32_t team = cm::loop_team_lanes(a.J, a.total_runs, (uint32_t)h->cu_count);
+  const uint64_t teams_per_block = 256u / team;
   const uint64_t want = (a.total_runs + teams_per_block - 1) / teams_per_block;
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * h->cu_count));
   hipError_t e;
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_loop(m->precision, a, blocks, stream)) != hipSuccess) return hip_fail(e, "closed-loop kernel");
+  if ((e = cm::launch_loop(m->precision, a, team, blocks, stream)) != hipSuccess)
+    return hip_fail(e, "closed-loop kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   return enqueue_score(m, s, r, stream);
 }

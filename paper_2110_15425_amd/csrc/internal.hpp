@@ -190,8 +190,8 @@ hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t st
 // uses to pack unfinished runs while a chunk drains.
 size_t lane_stage_bytes(int kind, int precision);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
-uint32_t loop_team_lanes(uint32_t J);
-hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st);
+uint32_t loop_team_lanes(uint32_t J, uint64_t runs, uint32_t cus);
+hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t team, uint32_t blocks, hipStream_t st);
 hipError_t launch_rnn_prep(const double* W, uint32_t n, void* out, bool bf16, hipStream_t st);
 hipError_t launch_rnn(int precision, const RnnArgs& a, uint32_t groups, hipStream_t st);
 hipError_t launch_uf_init(const UnfusedArgs& a, hipStream_t st);

@@ -12,17 +12,22 @@
 // evaluated in parallel (Sec. 3.6).
 //
 // Mapping: a team of P lanes (P = 1, 4, 16 or 64, the power of two that
-// covers the L^2 allocations, capped at a wavefront) owns one run at a time.
-// Lane i of the team evaluates allocations i, i + P, ... with all their
-// samples; a butterfly of P-lane shuffles then finds the best (score,
-// priority, allocation) and the second-best score, leaving the same result
-// in every lane.  Every lane of the team then applies the chosen step to its
-// own copy of the state (identical arithmetic, identical bits), so the team
-// never broadcasts and its control flow stays uniform.  Teams take runs in a
-// fixed stride, and a finished run is counted straight into global memory
-// by the team's first lane: a run costs L^2 M look-ahead steps per step, so
-// the atomics are negligible.  The allocation drive table [L^2][9][2] is
-// computed once per sweep by the preparation kernel.
+// covers the L^2 allocations, capped at a wavefront) owns one run at a time;
+// a search so wide that every lane of a workgroup still has four or more
+// allocations, over too few runs to fill the GPU with wavefront teams, takes
+// the whole workgroup (P = 256).  Lane i of the team evaluates allocations
+// i, i + P, ... with all their samples (four at a time when it has several,
+// so that independent random-number chains overlap); a butterfly of lane
+// shuffles, and for P = 256 a fold of the four wavefronts' results through
+// LDS, then finds the best (score, priority, allocation) and the second-best
+// score, leaving the same result in every lane.  Every lane of the team then
+// applies the chosen step to its own copy of the state (identical
+// arithmetic, identical bits), so the team never broadcasts and its control
+// flow stays uniform.  Teams take runs in a fixed stride, and a finished run
+// is counted straight into global memory by the team's first lane: a run
+// costs L^2 M look-ahead steps per step, so the atomics are negligible.  The
+// allocation drive table [L^2][9][2] is computed once per sweep by the
+// preparation kernel.
 #include "internal.hpp"
 #include "lca_step.hpp"
 #include "rng.hpp"
@@ -77,7 +82,16 @@ __device__ __forceinline__ bool tie_wins(uint32_t j, uint32_t bj, uint32_t k, ui
 
 template <int PREC, int P, int U>
 __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
-  const uint32_t j0 = (threadIdx.x & 63u) % (uint32_t)P;
+  // P = kLoopBlock: the whole workgroup is one team; its four wavefronts
+  // fold their results through LDS, double-buffered by the parity of a fold
+  // count that runs on across runs (consecutive folds use different buffers,
+  // so one barrier per fold suffices).  Every thread of the workgroup
+  // follows the same run and takes the same decisions, so the barrier is
+  // reached uniformly.
+  __shared__ double fold_v[2][kLoopBlock / 64], fold_s[2][kLoopBlock / 64];
+  __shared__ uint32_t fold_j[2][kLoopBlock / 64];
+  uint32_t folds = 0;
+  const uint32_t j0 = P > 64 ? threadIdx.x : (threadIdx.x & 63u) % (uint32_t)P;
   const uint32_t teams_per_block = kLoopBlock / P;
   const uint64_t n_teams = (uint64_t)gridDim.x * teams_per_block;
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -142,7 +156,7 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
         }
       }
 #pragma unroll
-      for (int off = 1; off < P; off <<= 1) {
+      for (int off = 1; off < (P < 64 ? P : 64); off <<= 1) {
         const double ov = __shfl_xor(bv, off, 64);
         const double os = __shfl_xor(sv, off, 64);
         const uint32_t oj = (uint32_t)__shfl_xor((int)bj, off, 64);
@@ -152,6 +166,29 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           bj = oj;
         }
         sv = ns;
+      }
+      if constexpr (P > 64) {
+        const uint32_t wv = threadIdx.x >> 6, par = folds++ & 1u;
+        if ((threadIdx.x & 63u) == 0) {
+          fold_v[par][wv] = bv;
+          fold_s[par][wv] = sv;
+          fold_j[par][wv] = bj;
+        }
+        __syncthreads();
+        bv = fold_v[par][0];
+        sv = fold_s[par][0];
+        bj = fold_j[par][0];
+#pragma unroll
+        for (uint32_t v = 1; v < kLoopBlock / 64; ++v) {
+          const double ov = fold_v[par][v], os = fold_s[par][v];
+          const uint32_t oj = fold_j[par][v];
+          const double ns = fmin(fmin(sv, os), fmax(bv, ov));
+          if (ov < bv || (ov == bv && tie_wins(oj, bj, k, t, s, k0, k1))) {
+            bv = ov;
+            bj = oj;
+          }
+          sv = ns;
+        }
       }
       if (sv > bv && sv - bv < eps) flag = true;
       // the step itself, with the chosen allocation, on the run's own stream
@@ -198,8 +235,11 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
 }
 
 template <int PREC>
-hipError_t launch_prec(const LoopArgs& a, uint32_t blocks, hipStream_t st) {
-  if (a.J == 1)
+hipError_t launch_prec(const LoopArgs& a, uint32_t team, uint32_t blocks, hipStream_t st) {
+  if (team == kLoopBlock)
+    hipLaunchKernelGGL((loop_kernel<PREC, kLoopBlock, kLoopChains>), dim3(blocks), dim3(kLoopBlock), 0,
+                       st, a);
+  else if (a.J == 1)
     hipLaunchKernelGGL((loop_kernel<PREC, 1, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
   else if (a.J <= 4)
     hipLaunchKernelGGL((loop_kernel<PREC, 4, 1>), dim3(blocks), dim3(kLoopBlock), 0, st, a);
@@ -214,12 +254,22 @@ hipError_t launch_prec(const LoopArgs& a, uint32_t blocks, hipStream_t st) {
 
 }  // namespace
 
-uint32_t loop_team_lanes(uint32_t J) { return J == 1 ? 1u : J <= 4 ? 4u : J <= 16 ? 16u : 64u; }
+// Lanes per run: the power of two covering the allocations, up to a
+// wavefront; a whole workgroup when every lane of it still has four or more
+// allocations and one-wavefront teams would leave the GPU short of
+// wavefronts (fewer than 8 per SIMD).
+uint32_t loop_team_lanes(uint32_t J, uint64_t runs, uint32_t cus) {
+  if (J >= 4u * kLoopBlock && runs < 32ull * cus) return kLoopBlock;
+  return J == 1 ? 1u : J <= 4 ? 4u : J <= 16 ? 16u : 64u;
+}
 
-hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t blocks, hipStream_t st) {
-  if (blocks < 1) return hipErrorInvalidValue;
-  return precision == CM_FP64 ? launch_prec<CM_FP64>(a, blocks, st)
-                              : launch_prec<CM_FP32_STEP>(a, blocks, st);
+// team: kLoopBlock, or the wavefront-or-smaller team loop_team_lanes gives
+// for a.J (any other value is rejected).
+hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t team, uint32_t blocks, hipStream_t st) {
+  if (blocks < 1 || (team != kLoopBlock && team != loop_team_lanes(a.J, ~0ull, 0u)))
+    return hipErrorInvalidValue;
+  return precision == CM_FP64 ? launch_prec<CM_FP64>(a, team, blocks, st)
+                              : launch_prec<CM_FP32_STEP>(a, team, blocks, st);
 }
 
 }  // namespace cm

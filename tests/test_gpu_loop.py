@@ -26,7 +26,11 @@ CASES = {
     # group ragged (289 = 4 x 64 + 33) or whole (1024 = 4 groups of 4 x 64)
     "levels17_chains": W.control_loop(trials=120, levels=17, samples=2, costs=[0.0, 0.02],
                                       seed=8),
-    "levels32_chains": W.control_loop(trials=60, levels=32, samples=1, costs=[0.003], seed=9),
+    # 1024 allocations: few runs take a whole workgroup per run (four
+    # wavefronts folding through LDS), many runs a wavefront each
+    "levels32_workgroup": W.control_loop(trials=60, levels=32, samples=1, costs=[0.003], seed=9),
+    "levels32_wavefront": W.control_loop(trials=4100, levels=32, samples=1, costs=[0.0, 0.003],
+                                         seed=10, max_steps=60, n_bins=6),
     "no_signals_short_cap": W.control_loop(trials=200, levels=5, samples=2, max_steps=15,
                                            n_bins=5),
     "nonneg": W.control_loop(trials=180, levels=4, samples=2, nonneg=1.0, costs=[0.0, 0.01]),
