@@ -172,13 +172,16 @@ typedef struct {
  * register-use versus occupancy trade-off the Distill paper measures on its
  * GPU kernels (Sec. 6.3) is what these choose between; cm_get_tuning
  * reports the stored values (runs_per_lane 0 = size-dependent).
- *  block          threads per workgroup (64..1024, multiple of 64).
+ *  block          threads per workgroup of the lane kernels; only 256 is
+ *                 supported (CM_E_UNSUPPORTED otherwise).
  *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane
  *                 (0: chosen per launch from the run count, 2..8).
  *  steps_per_sync lane-per-run kernels: steps between refills of finished
  *                 lanes (1..64; the DDM counts step pairs).  Defaults: 16
  *                 steps (LCA), 8 pairs (DDM).
- *  tile_rows      rate network: runs per workgroup tile (16, 32 or 64).
+ *  tile_rows      rate network: runs per workgroup tile, one 16-column
+ *                 matrix-core tile; only 16 is supported (the 256-unit
+ *                 network's W fragments fill the registers of a wider tile).
  *  lanes_per_run  DDM only: 1 (one lane per run), 64 (one wavefront per
  *                 run, 128 steps per prefix scan; runs_per_lane then counts
  *                 runs per wavefront) or 0 (per launch: 64 when every sweep

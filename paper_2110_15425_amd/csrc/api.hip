@@ -224,7 +224,7 @@ cm_tuning default_tuning(uint32_t kind, uint32_t prec) {
   t.block = 256;
   t.runs_per_lane = 0;
   t.steps_per_sync = kind == CM_DDM ? 8 : 16;  // DDM counts step pairs
-  t.tile_rows = 64;
+  t.tile_rows = 16;
   t.lanes_per_run = 0;  // DDM: chosen per launch (see plan_lane)
   (void)prec;
   return t;
@@ -831,8 +831,7 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
   if (v.block != 256) return fail(CM_E_UNSUPPORTED, "block must be 256");
   if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
   if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");
-  if (v.tile_rows != 16 && v.tile_rows != 32 && v.tile_rows != 64)
-    return fail(CM_E_INVALID, "tile_rows must be 16, 32 or 64");
+  if (v.tile_rows != 16) return fail(CM_E_UNSUPPORTED, "tile_rows must be 16");
   h->tune[kind][precision] = v;
   return ok();
 }

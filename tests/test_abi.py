@@ -138,3 +138,4 @@ def test_closed_loop_validation():
     m, s, keep = cm.structs(w, weights_ptr=8)
     n = C.c_uint64(0)
     assert cm.lib().cm_unfused_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)) == cm.E_UNSUPPORTED
+

@@ -51,3 +51,16 @@ def test_tuned_handle_cache_round_trip(tmp_path):
     assert table2 is None  # from the cache
     assert t2 == t1
     assert h2.get_tuning(W.LCA, W.FP64) == t1
+
+
+def test_fixed_knobs_are_refused_not_ignored():
+    """The workgroup size and the rate-network tile are fixed; other values
+    are refused as unsupported rather than accepted without effect."""
+    h = cm.Handle(0)
+    for bad in (dict(block=512), dict(tile_rows=32), dict(tile_rows=64)):
+        with pytest.raises(cm.CmError) as e:
+            h.set_tuning(W.RNN, W.BF16_PROJ, **bad)
+        assert e.value.status == cm.E_UNSUPPORTED, bad
+    h.set_tuning(W.RNN, W.BF16_PROJ, block=256, tile_rows=16)
+    t = h.get_tuning(W.RNN, W.BF16_PROJ)
+    assert (t["block"], t["tile_rows"]) == (256, 16)
