@@ -191,13 +191,32 @@ typedef struct {
   uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run;
 } cm_tuning;
 
-/* Pure host checks of a model/sweep pair; touches no device. */
+/* Pure host checks of a model/sweep pair (the rules above and the kind's
+ * parameter ranges: dt > 0, noise >= 0, thresholds > 0, |start| < theta,
+ * shapes); touches no device.  CM_E_INVALID or CM_E_UNSUPPORTED with the
+ * reason in cm_last_error(). */
 cm_status cm_validate(const cm_model *model, const cm_sweep *sweep);
 
-/* Workspace bytes a launch of this model/sweep needs (host only). */
+/* Workspace bytes a launch of this model/sweep needs (host only): the
+ * correct-response table, the conflict network's drive per (setting,
+ * stimulus) -- the loop-invariant work hoisted out of the step loop
+ * (Sec. 3.5) -- and the rate network's W in matrix-core fragment order.
+ * The caller allocates it (256-byte aligned) and may reuse it for any
+ * launch whose model and sweep need no more; the library writes it on the
+ * stream and it must not be shared by launches that may run concurrently. */
 cm_status cm_workspace_bytes(const cm_model *model, const cm_sweep *sweep, uint64_t *bytes);
 
-/* Handle bound to one HIP device: holds tuning and device properties. */
+/* A handle is bound to one HIP device (device_ordinal; CM_E_INVALID when
+ * out of range) and holds that device's properties, the tuning table and
+ * the serving slots; *out receives it.  Launches through a handle run on
+ * its device.  cm_destroy waits for work on the handle's serving slots,
+ * then releases the handle; NULL is accepted.  Several threads may launch
+ * through one handle while kernel timing (cm_profile) is off; the tuning
+ * table, timing and serving queue must be used from one thread.
+ * cm_set_tuning stores the launch shape for one (kind, precision) pair
+ * (fields as in cm_tuning; 0 = default), CM_E_INVALID or CM_E_UNSUPPORTED
+ * for values outside the ranges above; it changes launch shapes only,
+ * never results.  cm_get_tuning reports the stored values. */
 cm_status cm_create(int device_ordinal, cm_handle **out);
 cm_status cm_destroy(cm_handle *h);
 cm_status cm_set_tuning(cm_handle *h, uint32_t kind, uint32_t precision, const cm_tuning *t);
