@@ -65,7 +65,7 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "595e1c2dafc8c0d080b7e44fb6d47ea71aa18db8be5b28c88b77f25f4530aa54",
+TRAFFIC = {"sources_sha256": "03fb20f25fc0ff776806b6e829abc20fdffb082b9341d3dec1c9ef72a6d56e89",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md
            "bytes_per_launch": {6: 3317605, 8: 2828134}}
