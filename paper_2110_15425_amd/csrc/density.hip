@@ -23,15 +23,18 @@ constexpr int kMaxThreads = 1024;
 
 __device__ __forceinline__ double Phi(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
 
-// LDS index of kernel-row entry x (x >= -kFPad).  Threads own 8 consecutive
-// output cells, so within a wavefront their reads of the row are 8 doubles
-// apart; xor-ing bits 0-2 with bits 4-6 spreads every 16 such reads over the
-// 16 eight-byte LDS bank pairs (no conflicts), and maps each aligned block of
-// 128 entries onto itself.
-__device__ __forceinline__ uint32_t fidx(int x) {
-  const uint32_t u = (uint32_t)(x + kFPad);
-  return u ^ ((u >> 4) & 7u);
-}
+// LDS position of kernel-row entry x (x >= -kFPad), u = x + kFPad: one pad
+// slot after every 8 entries.  Threads own 8 consecutive output cells, so
+// within a wavefront their reads of the row are 8 entries, i.e. 9 slots (18
+// banks) apart: no two of them share a bank.  The 8 entries 8m..8m+7 sit
+// contiguously at 9m..9m+7, which lets the source loop read them as a group.
+__device__ __forceinline__ uint32_t fpos_u(uint32_t u) { return u + (u >> 3); }
+__device__ __forceinline__ uint32_t fpos(int x) { return fpos_u((uint32_t)(x + kFPad)); }
+
+// Logical and LDS sizes of the row: 2M - 1 entries after kFPad zeros, and up
+// to 8 past them read by the windows of output cells beyond M.
+__host__ __device__ inline uint32_t frow_entries(uint32_t M) { return ((2u * M + kFPad + 8u + 7u) / 8u) * 8u; }
+__host__ __device__ inline uint32_t frow_slots(uint32_t M) { return frow_entries(M) / 8u * 9u; }
 
 // Launch geometry, computed on the host: Q thread groups split the source
 // cells of each step, each group has TPQ threads (a multiple of 64 covering
@@ -43,9 +46,9 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
   const uint32_t Q = a.splits, TPQ = nt / Q, q = tid / TPQ, blk = tid - q * TPQ;
   const uint32_t nb = (M + kOut - 1) / kOut;
   const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  const uint32_t fsize = ((2 * M + kFPad + 8 + 127) / 128) * 128;  // see density_lds_bytes
-  double* f = sh;            // kernel row, swizzled, [fsize]
-  double* m0 = f + fsize;    // mass vectors [M]
+  const uint32_t fsize = frow_entries(M);
+  double* f = sh;                   // kernel row at fpos, [frow_slots]
+  double* m0 = f + frow_slots(M);   // mass vectors [M]
   double* m1 = m0 + M;
   double* part = m1 + M;     // partial sums of splits 1..Q-1, [Q-1][M]
   const uint64_t s = blockIdx.x;
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       const double k = (double)(x - (int)(M - 1));
       v = Phi(((k + 0.5) * h - as) / b) - Phi(((k - 0.5) * h - as) / b);
     }
-    f[fidx(x)] = v;
+    f[fpos_u(u)] = v;
   }
   // absorption tables of the cells this thread owns, tid + r nt (at most 8:
   // there are at least ceil(M / 8) threads)
@@ -124,16 +127,43 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       const int x0 = (int)jb - (int)i0 + (int)(M - 1);  // row entry of (jb, i0)
       double w[kOut];
 #pragma unroll
-      for (int k = 0; k < kOut; ++k) w[k] = f[fidx(x0 + k)];
-#pragma unroll 4
-      for (uint32_t i = i0; i < i1; ++i) {
+      for (int k = 0; k < kOut; ++k) w[k] = f[fpos(x0 + k)];
+      // Source i brings in entry x0 - 1 - (i - i0) (>= -1: a zero pad entry
+      // at the end).  Sources whose incoming entries fill an aligned group
+      // 8m+7 .. 8m are taken 8 at a time: the group is read at once and the
+      // window slides by register renaming.  u0 mod 8 is the same for every
+      // thread of the split group, so the lead and tail lengths are uniform.
+      const uint32_t u0 = (uint32_t)(x0 - 1 + kFPad);
+      const uint32_t lead = min((((u0 & 7u) + 1u) & 7u), i1 - i0);
+      auto one = [&](uint32_t i) {
         const double c = cur[i];
 #pragma unroll
         for (int k = 0; k < kOut; ++k) acc[k] = fma(c, w[k], acc[k]);
 #pragma unroll
         for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
-        w[0] = f[fidx(x0 - (int)(i - i0) - 1)];  // >= -1: a zero pad entry at the end
+        w[0] = f[fpos(x0 - (int)(i - i0) - 1)];
+      };
+      uint32_t i = i0;
+      for (; i < i0 + lead; ++i) one(i);
+      for (; i + 8u <= i1; i += 8u) {
+        const uint32_t ub = u0 - (i - i0);  // 8m + 7
+        const double* g = f + fpos_u(ub - 7u);
+        double nf[8], c8[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          nf[r] = g[r];
+          c8[r] = cur[i + r];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+          for (int k = 0; k < kOut; ++k) acc[k] = fma(c8[t], w[k], acc[k]);
+#pragma unroll
+          for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
+          w[0] = nf[7 - t];
+        }
       }
+      for (; i < i1; ++i) one(i);
       if (q > 0) {
         double* pq = part + (q - 1) * M;
 #pragma unroll
@@ -183,13 +213,10 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
 
 }  // namespace
 
-// The kernel row holds 2M - 1 entries after kFPad zeros; windows of invalid
-// output cells (beyond M) read up to 8 entries past it, and the swizzle stays
-// inside aligned blocks of 128, so the row is rounded up to whole blocks with
-// that margin.
+// LDS: the kernel row (frow_slots), two mass vectors and the partial sums of
+// splits 1..Q-1.
 size_t density_lds_bytes(uint32_t cells, uint32_t splits) {
-  const size_t fsize = ((2u * (size_t)cells + kFPad + 8 + 127) / 128) * 128;
-  return (fsize + 2u * (size_t)cells + (size_t)(splits - 1) * cells) * sizeof(double);
+  return ((size_t)frow_slots(cells) + 2u * (size_t)cells + (size_t)(splits - 1) * cells) * sizeof(double);
 }
 
 uint32_t density_threads_per_split(uint32_t cells) {
