@@ -35,6 +35,9 @@ __device__ __forceinline__ uint32_t fpos(int x) { return fpos_u((uint32_t)(x + k
 // to 8 past them read by the windows of output cells beyond M.
 __host__ __device__ inline uint32_t frow_entries(uint32_t M) { return ((2u * M + kFPad + 8u + 7u) / 8u) * 8u; }
 __host__ __device__ inline uint32_t frow_slots(uint32_t M) { return frow_entries(M) / 8u * 9u; }
+// Rows of the split groups' partial sums use the same padding (cell j at
+// j + j/8), so that threads writing 8 consecutive cells do not collide.
+__host__ __device__ inline uint32_t prow_slots(uint32_t M) { return (M + M / 8u + 2u) & ~1u; }
 
 // Launch geometry, computed on the host: Q thread groups split the source
 // cells of each step, each group has TPQ threads (a multiple of 64 covering
@@ -50,7 +53,8 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
   double* f = sh;                   // kernel row at fpos, [frow_slots]
   double* m0 = f + frow_slots(M);   // mass vectors [M]
   double* m1 = m0 + M;
-  double* part = m1 + M;     // partial sums of splits 1..Q-1, [Q-1][M]
+  double* part = m1 + M;     // partial sums of the Q splits, [Q][prow_slots]
+  const uint32_t PM = prow_slots(M);
   const uint64_t s = blockIdx.x;
   const double drift = a.n_signals ? a.grid[s * a.n_signals] : a.drift;
   const double as = drift * a.dt, b = a.b, th = a.thresh, h = (2.0 * th) / (double)M;
@@ -164,12 +168,10 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
         }
       }
       for (; i < i1; ++i) one(i);
-      if (q > 0) {
-        double* pq = part + (q - 1) * M;
+      double* pq = part + q * PM;
 #pragma unroll
-        for (int k = 0; k < kOut; ++k)
-          if (jb + k < M) pq[jb + k] = acc[k];
-      }
+      for (int k = 0; k < kOut; ++k)
+        if (jb + k < M) pq[fpos_u(jb + k)] = acc[k];
     }
     __syncthreads();
     if (tid == 0) {
@@ -181,14 +183,13 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       out_up[n - 1] = su;
       out_lo[n - 1] = sl;
     }
-    if (active && q == 0) {
-#pragma unroll
-      for (int k = 0; k < kOut; ++k) {
-        if (jb + k >= M) break;
-        double v = acc[k];
-        for (uint32_t r = 1; r < Q; ++r) v += part[(r - 1) * M + jb + k];
-        nxt[jb + k] = v;
-      }
+    // new mass of every cell: the splits' partial sums in split order, one
+    // cell per thread
+    for (uint32_t j = tid; j < M; j += nt) {
+      const uint32_t pj = fpos_u(j);
+      double v = part[pj];
+      for (uint32_t r = 1; r < Q; ++r) v += part[r * PM + pj];
+      nxt[j] = v;
     }
     __syncthreads();
     // survivor mass: stop once it is negligible
@@ -214,9 +215,9 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
 }  // namespace
 
 // LDS: the kernel row (frow_slots), two mass vectors and the partial sums of
-// splits 1..Q-1.
+// the splits.
 size_t density_lds_bytes(uint32_t cells, uint32_t splits) {
-  return ((size_t)frow_slots(cells) + 2u * (size_t)cells + (size_t)(splits - 1) * cells) * sizeof(double);
+  return ((size_t)frow_slots(cells) + 2u * (size_t)cells + (size_t)splits * prow_slots(cells)) * sizeof(double);
 }
 
 uint32_t density_threads_per_split(uint32_t cells) {
