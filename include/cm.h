@@ -254,7 +254,10 @@ cm_status cm_launch_batch(cm_handle *h, uint32_t n, const cm_model *models,
  * q(comp*(x0*x1)) with q(v) = v*2^32 rounded to nearest even and clamped to
  * +-2^62, summed modulo 2^64 (integer sums: independent of run order and
  * launch shape).  The DDM has one unit (x1 = 0).  Kinds CM_DDM and
- * CM_CONFLICT_LCA, precisions FP64 and FP32_STEP; 1 <= every <= max_steps. */
+ * CM_CONFLICT_LCA, precisions FP64 and FP32_STEP; 1 <= every <= max_steps.
+ * The launch rounds the tuned steps_per_sync to a multiple of the sampling
+ * interval (in step pairs for the DDM) when the interval is at most 64 of
+ * those units, so that the runs of a wavefront sample together. */
 cm_status cm_launch_timecourse(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
                                const cm_result *result, uint32_t every, int64_t *timecourse,
                                void *workspace, uint64_t workspace_bytes, void *hip_stream);

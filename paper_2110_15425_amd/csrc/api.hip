@@ -409,9 +409,22 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     a.tc = tc.out;
     a.tc_every = tc.every;
     a.tc_k = s->max_steps / tc.every;
+    // Runs start at the lane loop's sync points, so when the steps between
+    // sync points are a multiple of the sampling interval every run of a
+    // wavefront samples at the same steps and the wavefront takes the
+    // sampling branch once per interval instead of at several phases of it.
+    // The DDM advances in step pairs.
+    const uint32_t unit = m->kind == CM_DDM ? (tc.every % 2u ? tc.every : tc.every / 2u) : tc.every;
+    if (unit <= 64u) {
+      const uint32_t mult = std::max<uint32_t>(1u, (a.steps_per_sync + unit / 2u) / unit);
+      a.steps_per_sync = unit * std::min<uint32_t>(mult, 64u / unit);
+    }
   }
   const size_t rec_bytes = 4u * (cm::rec_words(B) + (tc.every ? cm::tc_words(a.tc_k) : 0u));
-  const uint64_t wmax = std::min<size_t>(kLdsBudget, h->lds_per_block) / rec_bytes;
+  // the lane kernel also stages its drain through LDS after the window
+  const size_t stage = scan ? 0 : cm::lane_stage_bytes((int)m->kind, (int)m->precision);
+  const uint64_t wmax =
+      std::min<size_t>(kLdsBudget, h->lds_per_block > stage ? h->lds_per_block - stage : 0) / rec_bytes;
   bool direct = false;
   // settings touched by one chunk: at most floor((chunk-1)/T) + 2
   if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
@@ -424,7 +437,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   a.window = direct ? 0 : (uint32_t)std::min<uint64_t>((chunk - 1) / T + 2, S);
   groups = (runs + chunk - 1) / chunk;
   lds = direct ? 0 : (size_t)a.window * rec_bytes;
-  if (!scan && !tc.every) lds += cm::lane_stage_bytes((int)m->kind, (int)m->precision);
+  lds += stage;
   return ok();
 }
 

@@ -38,6 +38,7 @@ struct Lane {
   int choice;      // -1 undecided
   bool flag;
   uint32_t next_sample;  // time-course variant: next sample step
+  uint32_t sample_k;     // time-course variant: index of that sample
 };
 
 // A lane's bookkeeping as it is staged through LDS while a workgroup drains
@@ -60,13 +61,31 @@ __device__ __forceinline__ uint64_t tc_quant(double v) {
   return (uint64_t)(int64_t)t;
 }
 
+// q(v) for |v| < 2^19, the same value in three instructions: v 2^32 is exact
+// and below 2^51 in magnitude, so adding 1.5 2^52 lands in [2^52, 2^53],
+// where the spacing is 1 and the one rounding of the sum is the
+// round-half-even of v 2^32 (1.5 2^52 is even); the integer then sits in the
+// low bits of the sum's encoding.
+__device__ __forceinline__ uint64_t tc_quant_small(double v) {
+  const double shift = 6755399441055744.0;  // 1.5 2^52, encoded 0x4338000000000000
+  return (uint64_t)__double_as_longlong(__builtin_fma(v, 4294967296.0, shift)) -
+         0x4338000000000000ull;
+}
+
 __device__ __forceinline__ void tc_add(unsigned long long* w, double x0, double x1, double comp) {
+  const double v[5] = {x0, x1, x0 * x0, x1 * x1, comp * (x0 * x1)};
+  const double small = 524288.0;  // 2^19
+  bool fits = true;
+  for (int i = 0; i < 5; ++i) fits &= fabs(v[i]) < small;
+  uint64_t q[5];
+  // the wavefront's sampling lanes take one form together
+  if (__builtin_expect(__builtin_amdgcn_ballot_w64(!fits) == 0, 1)) {
+    for (int i = 0; i < 5; ++i) q[i] = tc_quant_small(v[i]);
+  } else {
+    for (int i = 0; i < 5; ++i) q[i] = tc_quant(v[i]);
+  }
   atomicAdd(&w[0], 1ull);
-  atomicAdd(&w[1], (unsigned long long)tc_quant(x0));
-  atomicAdd(&w[2], (unsigned long long)tc_quant(x1));
-  atomicAdd(&w[3], (unsigned long long)tc_quant(x0 * x0));
-  atomicAdd(&w[4], (unsigned long long)tc_quant(x1 * x1));
-  atomicAdd(&w[5], (unsigned long long)tc_quant(comp * (x0 * x1)));
+  for (int i = 0; i < 5; ++i) atomicAdd(&w[1 + i], (unsigned long long)q[i]);
 }
 
 // Per-step hooks of the mechanisms.  NoSample compiles to nothing; Sample
@@ -84,7 +103,7 @@ struct Sample {
   __device__ __forceinline__ void operator()(Lane& L, double x0, double x1) const {
     if (__builtin_expect(L.n == L.next_sample, 0)) {
       L.next_sample += every;
-      const uint32_t k = L.n / every - 1u;
+      const uint32_t k = L.sample_k++;
       tc_add(base + ((uint64_t)(L.s - s_lo) * K + k) * kTcWords, x0, x1, comp);
     }
   }
@@ -462,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
     L.choice = -1;
     L.flag = false;
     L.next_sample = a.tc_every;
+    L.sample_k = 0;
     m.begin(a, L);
   };
   if (have) setup(off);
@@ -471,82 +491,69 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
     m.state(st);
     record(a, lds, s_lo, L, st, M::kWidth);
   };
-  if constexpr (TC) {
-    while (__any(have)) {
-      bool running = have;
-      if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
-      if (have && !running) {
-        finish();
-        off = atomicAdd(&next, 1u);
-        have = off < len;
-        if (have) setup(off);
-      }
+  // Refill from the chunk's queue while it lasts.
+  for (;;) {
+    // one LDS word, the same for the whole wavefront
+    if (__hip_atomic_load(&next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= len) break;
+    bool running = have;
+    if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
+    if (have && !running) {
+      finish();
+      off = atomicAdd(&next, 1u);
+      have = off < len;
+      if (have) setup(off);
     }
-    if (!a.direct) {
-      __syncthreads();
-      flush(a, lds, s_lo);
-    }
-  } else {
-    // Refill from the chunk's queue while it lasts.
-    for (;;) {
-      // one LDS word, the same for the whole wavefront
-      if (__hip_atomic_load(&next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= len) break;
-      bool running = have;
-      if (running) running = m.advance(a, L, k0, k1, (int)a.steps_per_sync, hook);
-      if (have && !running) {
-        finish();
-        off = atomicAdd(&next, 1u);
-        have = off < len;
-        if (have) setup(off);
-      }
-    }
-    // Drain: every kDrainSteps steps the workgroup packs its unfinished runs
-    // into the first wavefronts (through LDS); the wavefronts beyond the
-    // packed list wait at the barriers without issuing vector work, which
-    // leaves their issue slots to the other workgroups on the compute unit
-    // instead of stepping a few live lanes each.
-    M* stage_m = (M*)(lds + a.window * rec_words(a.n_bins));
-    LaneWords* stage_l = (LaneWords*)(stage_m + kBlock);
-    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (;;) {
-      __syncthreads();  // the stage's previous contents are consumed
-      const uint64_t act = __ballot(have);
-      if (lane == 0) drain_cnt[w] = (uint32_t)__popcll(act);
-      __syncthreads();
-      uint32_t base = 0, total = 0;
-      for (uint32_t v = 0; v < kBlock / 64; ++v) {
-        if (v < w) base += drain_cnt[v];
-        total += drain_cnt[v];
-      }
-      if (have) {
-        const uint32_t i = base + (uint32_t)__popcll(act & below);
-        stage_m[i] = m;
-        stage_l[i] = LaneWords{L.s, L.t, L.n, L.target, L.choice, L.flag ? 1u : 0u};
-      }
-      __syncthreads();
-      if (total == 0) break;  // every run of the chunk is recorded
-      const uint32_t i = w * 64u + lane;
-      have = i < total;
-      if (have) {
-        m = stage_m[i];
-        const LaneWords lw = stage_l[i];
-        L.s = lw.s;
-        L.t = lw.t;
-        L.n = lw.n;
-        L.target = lw.target;
-        L.choice = lw.choice;
-        L.flag = lw.flag != 0u;
-      }
-      bool running = have;
-      if (__any(running)) running = running && m.advance(a, L, k0, k1, kDrainSteps, hook);
-      if (have && !running) {
-        finish();
-        have = false;
-      }
-    }
-    if (!a.direct) flush(a, lds, s_lo);  // the last barrier follows every record
   }
+  // Drain: every kDrainSteps steps the workgroup packs its unfinished runs
+  // into the first wavefronts (through LDS); the wavefronts beyond the
+  // packed list wait at the barriers without issuing vector work, which
+  // leaves their issue slots to the other workgroups on the compute unit
+  // instead of stepping a few live lanes each.
+  M* stage_m = (M*)(lds + a.window * (rec_words(a.n_bins) + (TC ? tc_words(a.tc_k) : 0u)));
+  LaneWords* stage_l = (LaneWords*)(stage_m + kBlock);
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (;;) {
+    __syncthreads();  // the stage's previous contents are consumed
+    const uint64_t act = __ballot(have);
+    if (lane == 0) drain_cnt[w] = (uint32_t)__popcll(act);
+    __syncthreads();
+    uint32_t base = 0, total = 0;
+    for (uint32_t v = 0; v < kBlock / 64; ++v) {
+      if (v < w) base += drain_cnt[v];
+      total += drain_cnt[v];
+    }
+    if (have) {
+      const uint32_t i = base + (uint32_t)__popcll(act & below);
+      stage_m[i] = m;
+      stage_l[i] = LaneWords{L.s, L.t, L.n, L.target, L.choice, L.flag ? 1u : 0u};
+    }
+    __syncthreads();
+    if (total == 0) break;  // every run of the chunk is recorded
+    const uint32_t i = w * 64u + lane;
+    have = i < total;
+    if (have) {
+      m = stage_m[i];
+      const LaneWords lw = stage_l[i];
+      L.s = lw.s;
+      L.t = lw.t;
+      L.n = lw.n;
+      L.target = lw.target;
+      L.choice = lw.choice;
+      L.flag = lw.flag != 0u;
+      if constexpr (TC) {  // samples fall on multiples of tc_every
+        L.sample_k = L.n / a.tc_every;
+        L.next_sample = (L.sample_k + 1u) * a.tc_every;
+      }
+    }
+    bool running = have;
+    if (__any(running)) running = running && m.advance(a, L, k0, k1, kDrainSteps, hook);
+    if (have && !running) {
+      finish();
+      have = false;
+    }
+  }
+  if (!a.direct) flush(a, lds, s_lo);  // the last barrier follows every record
 }
 
 // Drift-diffusion with one wavefront per run.  Each lane draws one random

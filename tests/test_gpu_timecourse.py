@@ -77,6 +77,30 @@ def test_timecourse_fp32_against_fp32_oracle(kind):
     _compare(w, g_tc, o_tc, g_out, fp32=True)
 
 
+def test_timecourse_large_states():
+    """States far from the unit scale: squares beyond 2^19, where the kernel
+    quantises with the general rounding instead of its short form (both give
+    round-half-even of v 2^32), in waves that mix the two ranges."""
+    w, every = W.ddm(trials=40, drift=0.0, noise=400.0, thresh=3000.0, max_steps=2000,
+                     n_bins=10, seed=8), 7
+    h = cm.Handle(0)
+    g_out, g_tc = cm.timecourse(w, every, handle=h)
+    o_tc = oracle.timecourse(w, every)
+    assert g_tc.shape == o_tc.shape
+    assert np.abs(o_tc[0, :, 3]).max() > 2 ** 19 * S32  # the general form is reached
+    flagged = int(g_out["stats"][0, 8])
+    gc, oc = g_tc[0, :, 0], o_tc[0, :, 0]
+    assert np.all(np.abs(gc - oc) <= flagged)
+    same = gc == oc
+    # the walk's states agree to ~n ulps of |x| <= 3200: 1e-8 bounds the
+    # state difference and 2 * 3200 * 1e-8 that of the square
+    for c, dv in ((1, 1e-8), (3, 6.4e-5)):
+        d = (g_tc[0, :, c].astype(np.uint64) - o_tc[0, :, c].astype(np.uint64)).view(np.int64)
+        tol = gc * (S32 * dv + 1.0)
+        bad = same & (np.abs(d) > tol)
+        assert not bad.any(), (c, np.nonzero(bad)[0][:5], d[bad][:3])
+
+
 @pytest.mark.parametrize("kind", ["ddm", "lca"])
 def test_timecourse_independent_of_launch_shape(kind):
     """Integer sums: identical bits for every launch shape and for the
