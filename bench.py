@@ -65,10 +65,10 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "03fb20f25fc0ff776806b6e829abc20fdffb082b9341d3dec1c9ef72a6d56e89",
+TRAFFIC = {"sources_sha256": "fcd5c41135d367008cb139596767630e897234f9a78f42f13e5960a2a621cab5",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md
-           "bytes_per_launch": {6: 3317605, 8: 2828134}}
+           "bytes_per_launch": {6: 3315557, 8: 2826086}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
 
