@@ -52,3 +52,20 @@ def test_density_cell_count_extremes(cells):
         lo, up = oracle.ddm_density(d * 0.01, math.sqrt(0.01), 1.0, cells=cells, max_steps=400)
         np.testing.assert_allclose(out[s, 0], lo, rtol=0, atol=1e-12)
         np.testing.assert_allclose(out[s, 1], up, rtol=0, atol=1e-12)
+
+
+def test_density_64_drifts_full_size_sampled():
+    """The 64-setting sweep at full size (1000 cells, 3000 steps, tol 1e-15),
+    one workgroup per setting as timed: three settings against the oracle."""
+    drifts = [0.3 * (i + 1) / 64 for i in range(64)]
+    w = W.ddm(drifts=drifts)
+    out = cm.ddm_density(w, cells=1000, tol=1e-15)
+    assert out.shape == (64, 2, 3000)
+    for s in (0, 37, 63):
+        lo, up = oracle.ddm_density(drifts[s] * 0.01, math.sqrt(0.01), 1.0, cells=1000,
+                                    max_steps=3000, tol=1e-15)
+        np.testing.assert_allclose(out[s, 0], lo, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(out[s, 1], up, rtol=0, atol=1e-12)
+    # the drift orders the settings: more drift, more mass on the upper bound
+    upper = out[:, 1].sum(axis=1)
+    assert np.all(np.diff(upper) > 0)
