@@ -68,7 +68,7 @@ uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
-  uint64_t drive, correct, wfrag, total;
+  uint64_t drive, correct, cost, wfrag, total;
 };
 
 Layout layout(const cm_model* m, const cm_sweep* s) {
@@ -80,7 +80,8 @@ Layout layout(const cm_model* m, const cm_sweep* s) {
   if (m->kind == CM_CONFLICT_LCA) off = align_up(off + s->n_settings * 9u * 2u * sizeof(double), kWorkspaceAlign);
   if (m->kind == CM_CONFLICT_LOOP) {
     const uint64_t lv = (uint64_t)m->params[CM_LOOP_LEVELS];  // validated before any layout is used
-    off = align_up(off + lv * lv * 9u * 2u * sizeof(double), kWorkspaceAlign);
+    L.cost = off + lv * lv * 9u * 2u * sizeof(double);  // after the drive table
+    off = align_up(L.cost + lv * lv * sizeof(double), kWorkspaceAlign);
   }
   L.wfrag = off;
   if (m->kind == CM_RATE_RNN) {
@@ -485,6 +486,7 @@ void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* w
     it.d.weights = m->weights;
     it.d.drive = (double*)(ws + L.drive);
     it.d.correct = (int32_t*)(ws + L.correct);
+    it.d.cost = (double*)(ws + L.cost);
     tables = 9 + it.d.n_settings * 9u;
   }
   it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + it.n_extra + tables;
@@ -590,9 +592,9 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   a.leak = p[CM_LCA_LEAK];
   a.comp = p[CM_LCA_COMP];
   a.cost = p[CM_LOOP_COST];
-  a.amax = p[CM_LOOP_AMAX];
   a.grid = s->grid;
   a.drive = (const double*)(ws + L.drive);
+  a.norm2 = (const double*)(ws + L.cost);
   a.correct = (const int32_t*)(ws + L.correct);
   a.hist = r->hist;
   a.stats = r->stats;

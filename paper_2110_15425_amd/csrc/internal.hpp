@@ -85,6 +85,7 @@ struct DriveArgs {
   const double* grid;
   double* drive;     // [settings][9][2]
   int32_t* correct;  // [9]
+  double* cost;      // closed loop: [allocations] c_A^2 + c_B^2, else NULL
 };
 
 // Per-sweep preparation, many sweeps per launch: zero the histogram and
@@ -158,9 +159,10 @@ struct LoopArgs {
   uint64_t trials, n_settings, total_runs, seed;
   uint64_t steps_magic;
   uint32_t max_steps, n_bins, n_signals, L, J, M, nonneg, pad;
-  double thresh, flag_eps, b, dt, leak, comp, cost, amax;
+  double thresh, flag_eps, b, dt, leak, comp, cost;
   const double* grid;      // [n_settings] control-cost weights, or NULL
   const double* drive;     // [J][9][2]
+  const double* norm2;     // [J] c_A^2 + c_B^2 of allocation j
   const int32_t* correct;  // [9]
   uint64_t* hist;
   uint64_t* stats;

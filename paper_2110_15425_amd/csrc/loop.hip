@@ -26,8 +26,8 @@
 // flow stays uniform.  Teams take runs in a fixed stride, and a finished run
 // is counted straight into global memory by the team's first lane: a run
 // costs L^2 M look-ahead steps per step, so the atomics are negligible.  The
-// allocation drive table [L^2][9][2] is computed once per sweep by the
-// preparation kernel.
+// allocation drive table [L^2][9][2] and the allocations' squared norms
+// c_A^2 + c_B^2 [L^2] are computed once per sweep by the preparation kernel.
 #include "internal.hpp"
 #include "lca_step.hpp"
 #include "rng.hpp"
@@ -65,10 +65,6 @@ __device__ __forceinline__ void lca_step(const LoopArgs& a, double x0, double x1
   }
 }
 
-__device__ __forceinline__ double level(const LoopArgs& a, uint32_t i) {
-  return a.L == 1 ? a.amax : (a.amax * (double)i) / (double)(a.L - 1);
-}
-
 // Tie rule among allocations with equal scores: the smaller (Philox priority,
 // allocation) wins.  kNone stands for "no allocation yet".
 __device__ __forceinline__ bool tie_wins(uint32_t j, uint32_t bj, uint32_t k, uint32_t t, uint32_t s,
@@ -103,6 +99,10 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
     const uint32_t stim = t % 9u;
     const int c = a.correct[stim];
     const double kappa = a.n_signals ? a.grid[s] : a.cost;
+    // the mean over M samples: a power of two divides exactly as a product
+    // with its reciprocal, which saves a division per allocation and step
+    const bool pow2 = (M & (M - 1u)) == 0u;
+    const double inv_m = 1.0 / (double)M;
     double x0 = 0.0, x1 = 0.0;
     bool flag = false;
     int choice = -1;
@@ -141,8 +141,8 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
         for (uint32_t u = 0; u < U; ++u) {
           if (j + u * P >= J) break;
           const uint32_t jj = ju[u];
-          const double cA = level(a, jj / a.L), cB = level(a, jj % a.L);
-          const double V = kappa * (cA * cA + cB * cB) - gs[u] / (double)M;
+          const double mean = pow2 ? gs[u] * inv_m : gs[u] / (double)M;
+          const double V = kappa * a.norm2[jj] - mean;
           if (V < bv) {
             sv = bv;
             bv = V;
