@@ -17,8 +17,8 @@
 // allocations, over too few runs to fill the GPU with wavefront teams, takes
 // the whole workgroup (P = 256).  Lane i of the team evaluates allocations
 // i, i + P, ... with all their samples (four at a time when it has several,
-// so that independent random-number chains overlap); a butterfly of lane
-// shuffles, and for P = 256 a fold of the four wavefronts' results through
+// so that independent random-number chains overlap); a butterfly of
+// cross-lane moves (DPP within 16-lane rows, shuffles across them), and for P = 256 a fold of the four wavefronts' results through
 // LDS, then finds the best (score, priority, allocation) and the second-best
 // score, leaving the same result in every lane.  Every lane of the team then
 // applies the chosen step to its own copy of the state (identical
@@ -28,6 +28,8 @@
 // costs L^2 M look-ahead steps per step, so the atomics are negligible.  The
 // allocation drive table [L^2][9][2] and the allocations' squared norms
 // c_A^2 + c_B^2 [L^2] are computed once per sweep by the preparation kernel.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "lca_step.hpp"
 #include "rng.hpp"
@@ -74,6 +76,29 @@ __device__ __forceinline__ bool tie_wins(uint32_t j, uint32_t bj, uint32_t k, ui
   const uint32_t pj = philox(k, t, s, kStreamPick | j, k0, k1).w0;
   const uint32_t pb = philox(k, t, s, kStreamPick | bj, k0, k1).w0;
   return pj < pb || (pj == pb && j < bj);
+}
+
+// The partner's value in round r of a team's reduction; each round joins the
+// two halves of aligned lane groups of 2^(r+1).  Rounds 0-3 stay within a
+// 16-lane row and use DPP moves (swap pairs, swap pairs of pairs, mirror
+// within 8, mirror within 16: no LDS round trip); rounds 4 and 5 cross rows
+// by lane shuffles.  The reduction's combine is commutative and associative,
+// so any pairing that joins the two halves of each group gives the same
+// result in every lane.
+template <int R>
+__device__ __forceinline__ uint32_t partner(uint32_t v) {
+  if constexpr (R == 0) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (R == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (R == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);
+  else if constexpr (R == 3) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);
+  else return (uint32_t)__shfl_xor((int)v, 1 << R, 64);
+}
+
+template <int R>
+__device__ __forceinline__ double partner(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = partner<R>((uint32_t)u), hi = partner<R>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
 template <int PREC, int P, int U>
@@ -155,18 +180,25 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           }
         }
       }
-#pragma unroll
-      for (int off = 1; off < (P < 64 ? P : 64); off <<= 1) {
-        const double ov = __shfl_xor(bv, off, 64);
-        const double os = __shfl_xor(sv, off, 64);
-        const uint32_t oj = (uint32_t)__shfl_xor((int)bj, off, 64);
-        const double ns = fmin(fmin(sv, os), fmax(bv, ov));
-        if (ov < bv || (ov == bv && tie_wins(oj, bj, k, t, s, k0, k1))) {
-          bv = ov;
-          bj = oj;
+      auto join = [&](auto round) {
+        constexpr int R = decltype(round)::value;
+        if constexpr ((1 << R) < (P < 64 ? P : 64)) {
+          const double ov = partner<R>(bv), os = partner<R>(sv);
+          const uint32_t oj = partner<R>(bj);
+          const double ns = fmin(fmin(sv, os), fmax(bv, ov));
+          if (ov < bv || (ov == bv && tie_wins(oj, bj, k, t, s, k0, k1))) {
+            bv = ov;
+            bj = oj;
+          }
+          sv = ns;
         }
-        sv = ns;
-      }
+      };
+      join(std::integral_constant<int, 0>{});
+      join(std::integral_constant<int, 1>{});
+      join(std::integral_constant<int, 2>{});
+      join(std::integral_constant<int, 3>{});
+      join(std::integral_constant<int, 4>{});
+      join(std::integral_constant<int, 5>{});
       if constexpr (P > 64) {
         const uint32_t wv = threadIdx.x >> 6, par = folds++ & 1u;
         if ((threadIdx.x & 63u) == 0) {
