@@ -344,8 +344,9 @@ struct TcSpec {
 // runs per lane, which trades GPU fill against the tail of each chunk).
 
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
-                    const Layout& L, bool scan, uint64_t launch_runs, const TcSpec& tc,
+                    const Layout& L, uint32_t scan_block, uint64_t launch_runs, const TcSpec& tc,
                     cm::SimArgs& a, uint64_t& groups, size_t& lds) {
+  const bool scan = scan_block != 0;
   const cm_tuning& tune = h->tune[m->kind][m->precision];
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
@@ -393,14 +394,19 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   uint64_t rpl = tune.runs_per_lane;
   uint64_t chunk;
   if (scan) {
-    // One wavefront per run: a workgroup of 4 wavefronts takes 4 runs per
+    // One wavefront per run: a workgroup of W wavefronts takes W runs per
     // round.  More runs per wavefront lengthen each wavefront's serial chain;
     // fewer mean more workgroups, each flushing its histogram window with
     // atomics into the same few global counters.  The two costs balance near
-    // runs per wavefront ~ sqrt(runs / 600) (measured on MI355X: 2 at 2,000
-    // runs, 4 at 10^4, 4-8 at 5x10^4).
-    if (!rpl) rpl = std::max<uint64_t>(1, std::min<uint64_t>(64, (uint64_t)llround(sqrt((double)runs / 600.0))));
-    chunk = 4u * rpl;
+    // a chunk of 4 sqrt(runs / 600) runs (measured on MI355X with 4
+    // wavefronts: 2 runs per wavefront at 2,000 runs, 4 at 10^4, 4-8 at
+    // 5x10^4); 8 wavefronts per workgroup keep that chunk with half the
+    // serial chain.
+    const uint32_t waves = scan_block / 64u;
+    if (!rpl)
+      rpl = std::max<uint64_t>(
+          1, std::min<uint64_t>(64, (uint64_t)llround(4.0 * sqrt((double)runs / 600.0) / waves)));
+    chunk = (uint64_t)waves * rpl;
   } else {
     if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(8, launch_runs / (4096ull * h->cu_count)));
     chunk = (uint64_t)tune.block * rpl;
@@ -630,6 +636,10 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   }
   uint64_t launch_runs = 0;
   for (uint32_t k = 0; k < n; ++k) launch_runs += ss[idx[k]].n_settings * ss[idx[k]].trials;
+  // the scan form: 8 wavefronts per workgroup while the launch is small (more
+  // wavefronts in flight for the same number of histogram flushes; measured
+  // on MI355X: 10-12 % faster at 10^4 runs, even at 10^5, slower at 10^6)
+  const uint32_t scan_block = scan ? (launch_runs <= (1ull << 17) ? 512u : 256u) : 0u;
   cm::LaneBatch b{};
   b.n = n;
   size_t lds = 0;
@@ -639,7 +649,7 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     uint64_t groups = 0;
     size_t l = 0;
     cm_status st =
-        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan, launch_runs, tc, b.a[k], groups, l);
+        plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan_block, launch_runs, tc, b.a[k], groups, l);
     if (st != CM_OK) return st;
     b.base[k] = base;
     base += groups;
@@ -658,7 +668,7 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   if ((e = cm::launch_prep(pb, stream)) != hipSuccess) return hip_fail(e, "sweep preparation");
   ProfScope prof{h, stream};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan, tc.every != 0, b, lds, stream)) != hipSuccess)
+  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan_block, tc.every != 0, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_score(sb, stream)) != hipSuccess) return hip_fail(e, "score kernel");

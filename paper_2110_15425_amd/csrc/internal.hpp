@@ -183,7 +183,9 @@ struct DensityArgs {
 };
 
 // Launchers (return the hipError_t of the launch).
-hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const LaneBatch& b,
+// scan_block: 0 for the lane kernel, else the DDM scan kernel with that many
+// threads (256 or 512) per workgroup.
+hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, const LaneBatch& b,
                            size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,

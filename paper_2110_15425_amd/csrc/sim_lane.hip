@@ -29,6 +29,7 @@ namespace cm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kScanBlockMax = 512;  // the scan kernel runs 256 or 512 threads per workgroup
 constexpr int kDrainSteps = 16;  // steps between packings once a chunk's queue is empty
 
 struct Lane {
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
 // increments in a different order than the sequential update; the results
 // differ by rounding only (far below the flag distance).
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
+__global__ __launch_bounds__(kScanBlockMax) void ddm_scan_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];
   uint32_t* lds = (uint32_t*)lds_u64;
   uint32_t sw = 0;
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void ddm_scan_kernel(LaneBatch batch) {
     for (uint32_t i = threadIdx.x; i < a.window * rec_words(a.n_bins); i += blockDim.x) lds[i] = 0u;
   __syncthreads();
 
-  // The four wavefronts take the chunk's runs round-robin.  Every loop exit
+  // The wavefronts take the chunk's runs round-robin.  Every loop exit
   // depends only on wave-uniform values (scalar registers), so each loop is
   // left by the whole wavefront at once and needs no per-lane bookkeeping.
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -700,14 +701,16 @@ hipError_t launch_model(const LaneBatch& b, bool tc, size_t lds, hipStream_t st)
 
 }  // namespace
 
-hipError_t launch_sim_lane(int kind, int precision, bool scan, bool tc, const LaneBatch& b,
+hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, const LaneBatch& b,
                            size_t lds_bytes, hipStream_t st) {
-  if (b.n < 1 || b.n > kMaxBatch || (scan && tc)) return hipErrorInvalidValue;
-  if (kind == CM_DDM && scan) {
+  if (b.n < 1 || b.n > kMaxBatch || (scan_block && tc)) return hipErrorInvalidValue;
+  if (scan_block) {
+    if (kind != CM_DDM || (scan_block != 256u && scan_block != (uint32_t)kScanBlockMax))
+      return hipErrorInvalidValue;
     if (precision == CM_FP64)
-      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP64>), dim3(b.base[b.n]), dim3(kBlock), lds_bytes, st, b);
+      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP64>), dim3(b.base[b.n]), dim3(scan_block), lds_bytes, st, b);
     else
-      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP32_STEP>), dim3(b.base[b.n]), dim3(kBlock), lds_bytes, st, b);
+      hipLaunchKernelGGL((ddm_scan_kernel<CM_FP32_STEP>), dim3(b.base[b.n]), dim3(scan_block), lds_bytes, st, b);
     return hipGetLastError();
   }
   if (kind == CM_DDM)
