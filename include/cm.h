@@ -185,8 +185,11 @@ typedef struct {
  *  lanes_per_run  DDM only: 1 (one lane per run), 64 (one wavefront per
  *                 run, 128 steps per prefix scan; runs_per_lane then counts
  *                 runs per wavefront) or 0 (per launch: 64 when every sweep
- *                 of the launch has at most 2^20 runs, else 1).  Results do
- *                 not depend on this choice. */
+ *                 of the launch has at most 2^20 runs, else 1).  The
+ *                 wavefront form runs 8 wavefronts per workgroup when the
+ *                 launch has at most 2^17 runs, else 4 (the block knob
+ *                 does not apply to it).  Results do not depend on these
+ *                 choices. */
 typedef struct {
   uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run;
 } cm_tuning;
