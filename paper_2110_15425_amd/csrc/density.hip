@@ -45,6 +45,7 @@ __host__ __device__ inline uint32_t prow_slots(uint32_t M) { return (M + M / 8u 
 __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a) {
   extern __shared__ double sh[];
   __shared__ double red[2][kMaxThreads / 64];
+  __shared__ double red_sv[kMaxThreads / 64];
   const uint32_t M = a.cells, tid = threadIdx.x, nt = blockDim.x;
   const uint32_t Q = a.splits, TPQ = nt / Q, q = tid / TPQ, blk = tid - q * TPQ;
   const uint32_t nb = (M + kOut - 1) / kOut;
@@ -55,6 +56,8 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
   double* m1 = m0 + M;
   double* part = m1 + M;     // partial sums of the Q splits, [Q][prow_slots]
   const uint32_t PM = prow_slots(M);
+  double* upc = part + Q * PM;  // per cell: mass absorbed at the upper bound in one step
+  double* loc = upc + M;        // and at the lower bound
   const uint64_t s = blockIdx.x;
   const double drift = a.n_signals ? a.grid[s * a.n_signals] : a.drift;
   const double as = drift * a.dt, b = a.b, th = a.thresh, h = (2.0 * th) / (double)M;
@@ -71,18 +74,12 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
     }
     f[fpos_u(u)] = v;
   }
-  // absorption tables of the cells this thread owns, tid + r nt (at most 8:
-  // there are at least ceil(M / 8) threads)
-  double upc[kOut], loc[kOut];
-#pragma unroll
-  for (int r = 0; r < kOut; ++r) {
-    const uint32_t i = tid + (uint32_t)r * nt;
-    upc[r] = 0.0;
-    loc[r] = 0.0;
-    if (i >= M) continue;
+  // absorption tables (in LDS, so that the registers hold the convolution's
+  // window and sums)
+  for (uint32_t i = tid; i < M; i += nt) {
     const double c = -th + ((double)i + 0.5) * h;
-    upc[r] = Phi(-((th - c) - as) / b);
-    loc[r] = Phi(((-th - c) - as) / b);
+    upc[i] = Phi(-((th - c) - as) / b);
+    loc[i] = Phi(((-th - c) - as) / b);
     // first step from the start point, exact
     const double x0 = a.start;
     const double e0 = -th + (double)i * h, e1 = -th + (double)(i + 1) * h;
@@ -104,13 +101,9 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
   for (; n <= a.max_steps; ++n) {
     // absorbed at step n
     double pu = 0.0, pl = 0.0;
-#pragma unroll
-    for (int r = 0; r < kOut; ++r) {
-      const uint32_t i = tid + (uint32_t)r * nt;
-      if (i < M) {
-        pu = fma(cur[i], upc[r], pu);
-        pl = fma(cur[i], loc[r], pl);
-      }
+    for (uint32_t i = tid; i < M; i += nt) {
+      pu = fma(cur[i], upc[i], pu);
+      pl = fma(cur[i], loc[i], pl);
     }
     for (int o = 32; o > 0; o >>= 1) {
       pu += __shfl_xor(pu, o, 64);
@@ -149,7 +142,7 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       };
       uint32_t i = i0;
       for (; i < i0 + lead; ++i) one(i);
-      for (; i + 8u <= i1; i += 8u) {
+      auto group = [&](uint32_t i) {
         const uint32_t ub = u0 - (i - i0);  // 8m + 7
         const double* g = f + fpos_u(ub - 7u);
         double nf[8], c8[8];
@@ -166,6 +159,16 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
           for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
           w[0] = nf[7 - t];
         }
+      };
+      // two groups per iteration: the window then returns to its registers
+      // every 16 sources rather than every 8 (fewer register moves)
+      for (; i + 16u <= i1; i += 16u) {
+        group(i);
+        group(i + 8u);
+      }
+      if (i + 8u <= i1) {
+        group(i);
+        i += 8u;
       }
       for (; i < i1; ++i) one(i);
       double* pq = part + q * PM;
@@ -184,27 +187,28 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       out_lo[n - 1] = sl;
     }
     // new mass of every cell: the splits' partial sums in split order, one
-    // cell per thread
+    // cell per thread; and the survivor mass, to stop once it is negligible
+    double sv = 0.0;
     for (uint32_t j = tid; j < M; j += nt) {
       const uint32_t pj = fpos_u(j);
       double v = part[pj];
       for (uint32_t r = 1; r < Q; ++r) v += part[r * PM + pj];
       nxt[j] = v;
+      sv += v;
     }
-    __syncthreads();
-    // survivor mass: stop once it is negligible
-    double sv = 0.0;
-    for (uint32_t j = tid; j < M; j += nt) sv += nxt[j];
     for (int o = 32; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
-    if (lane == 0) red[0][wave] = sv;
+    if (lane == 0) red_sv[wave] = sv;
+    // One barrier per step besides the one after the partial sums: the next
+    // step's reads of the new mass and writes of partial sums and of red
+    // come after it, and every read of this step's partial sums and red
+    // comes before it.
     __syncthreads();
     double tot = 0.0;
-    for (int w = 0; w < nw; ++w) tot += red[0][w];
+    for (int w = 0; w < nw; ++w) tot += red_sv[w];
     double* t = cur;
     cur = nxt;
     nxt = t;
     if (tot < a.tol) break;
-    __syncthreads();
   }
   for (uint32_t k = n + 1 + tid; k <= a.max_steps; k += nt) {
     out_up[k - 1] = 0.0;
@@ -214,10 +218,10 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
 
 }  // namespace
 
-// LDS: the kernel row (frow_slots), two mass vectors and the partial sums of
-// the splits.
+// LDS: the kernel row (frow_slots), two mass vectors, the partial sums of
+// the splits and the two absorption tables.
 size_t density_lds_bytes(uint32_t cells, uint32_t splits) {
-  return ((size_t)frow_slots(cells) + 2u * (size_t)cells + (size_t)splits * prow_slots(cells)) * sizeof(double);
+  return ((size_t)frow_slots(cells) + 4u * (size_t)cells + (size_t)splits * prow_slots(cells)) * sizeof(double);
 }
 
 uint32_t density_threads_per_split(uint32_t cells) {
