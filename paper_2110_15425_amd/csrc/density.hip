@@ -23,6 +23,35 @@ constexpr int kMaxThreads = 1024;
 
 __device__ __forceinline__ double Phi(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
 
+// A double from another lane: DPP patterns within 16-lane rows (swap pairs,
+// swap pairs of pairs, mirror within 8, mirror within 16), lane shuffles
+// across rows.  Round r joins the halves of aligned groups of 2^(r+1) lanes.
+template <int R>
+__device__ __forceinline__ double partner(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  constexpr int ctrl = R == 0 ? 0xB1 : R == 1 ? 0x4E : R == 2 ? 0x141 : 0x140;
+  if constexpr (R < 4) {
+    lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, ctrl, 0xF, 0xF, false);
+    hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, ctrl, 0xF, 0xF, false);
+  } else {
+    lo = (uint32_t)__shfl_xor((int)lo, 1 << R, 64);
+    hi = (uint32_t)__shfl_xor((int)hi, 1 << R, 64);
+  }
+  return __longlong_as_double((long long)((uint64_t)lo | ((uint64_t)hi << 32)));
+}
+
+// Sum over the wavefront, the same value in every lane (all lanes active).
+__device__ __forceinline__ double wave_sum(double v) {
+  v += partner<0>(v);
+  v += partner<1>(v);
+  v += partner<2>(v);
+  v += partner<3>(v);
+  v += partner<4>(v);
+  v += partner<5>(v);
+  return v;
+}
+
 // LDS position of kernel-row entry x (x >= -kFPad), u = x + kFPad: one pad
 // slot after every 8 entries.  Threads own 8 consecutive output cells, so
 // within a wavefront their reads of the row are 8 entries, i.e. 9 slots (18
@@ -105,10 +134,8 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       pu = fma(cur[i], upc[i], pu);
       pl = fma(cur[i], loc[i], pl);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      pu += __shfl_xor(pu, o, 64);
-      pl += __shfl_xor(pl, o, 64);
-    }
+    pu = wave_sum(pu);
+    pl = wave_sum(pl);
     if (lane == 0) {
       red[0][wave] = pu;
       red[1][wave] = pl;
@@ -196,7 +223,7 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
       nxt[j] = v;
       sv += v;
     }
-    for (int o = 32; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 64);
+    sv = wave_sum(sv);
     if (lane == 0) red_sv[wave] = sv;
     // One barrier per step besides the one after the partial sums: the next
     // step's reads of the new mass and writes of partial sums and of red
