@@ -122,7 +122,17 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
 
   // this thread's share of the convolution: output cells jb..jb+7 from the
   // source cells [i0, i1) of its group
-  const uint32_t jb = blk * kOut, i0 = (q * M) / Q, i1 = ((q + 1) * M) / Q;
+  // Split boundaries after the first sit at sources i = M - 1 (mod 8): there
+  // the incoming row entries of every output block start an aligned group,
+  // so only the first split has a lead of single sources (and only the last
+  // a tail of one).
+  auto split_start = [&](uint32_t g) -> uint32_t {
+    if (g == 0u) return 0u;
+    if (g >= Q) return M;
+    const uint32_t base = (g * M) / Q, r = (M - 1u) & 7u;
+    return base < r ? 0u : base - ((base - r) & 7u);
+  };
+  const uint32_t jb = blk * kOut, i0 = split_start(q), i1 = split_start(q + 1u);
   const bool active = blk < nb;
   double* cur = m0;
   double* nxt = m1;
