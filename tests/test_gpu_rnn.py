@@ -98,3 +98,34 @@ def test_rnn_invariant_to_dumps():
     w = _case(256, 3000, seed=9, precision=W.BF16_PROJ)
     a, b = cm.run(w), cm.run(w, dumps=True)
     assert np.array_equal(a["hist"], b["hist"]) and np.array_equal(a["stats"], b["stats"])
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.BF16_PROJ])
+def test_rnn_coupled_fixed_point(prec):
+    """Two groups of 32 units, coupled within and across groups with
+    different strengths each way, no noise, no input: every run settles at
+    the fixed point of the continuous dynamics, found by root finding
+    (bf16 weights move it by their rounding)."""
+    from scipy.optimize import fsolve
+    a, b, c_ab, c_ba = 1.0, -0.5, 0.8, -0.6
+    nu, h = 64, 32
+    Wm = np.zeros((nu, nu))
+    Wm[:h, :h] = a / (h - 1)
+    Wm[:h, h:] = c_ab / h
+    Wm[h:, :h] = c_ba / h
+    Wm[h:, h:] = b / (h - 1)
+    np.fill_diagonal(Wm, 0.0)
+    wts = np.concatenate([Wm.ravel(), np.zeros(2 * nu)])
+    w = W.rnn(trials=40, seed=5, n_units=nu, dt=0.05, noise=0.0, thresh=1e300, input_gain=0.0,
+              max_steps=1500, n_bins=10, weights=wts, precision=prec)
+    g = cm.run(w, dumps=True)
+
+    def s(x):
+        return 1.0 / (1.0 + np.exp(-x))
+
+    xa, xb = fsolve(lambda v: [v[0] - a * s(v[0]) - c_ab * s(v[1]),
+                               v[1] - c_ba * s(v[0]) - b * s(v[1])], [0.5, -0.5], xtol=1e-14)
+    tol = 1e-9 if prec == W.FP64 else 2e-2
+    x = g["run_state"][:, 2:]
+    assert np.abs(x[:, :h] - xa).max() < tol and np.abs(x[:, h:] - xb).max() < tol
+    assert int(g["stats"][0, 2]) == 40  # undecided at the cap

@@ -110,3 +110,47 @@ def test_reduced_precision_close_to_fp64(prec):
     pa = a["hist"][0] / 512
     pb = b["hist"][0] / 512
     assert np.abs(pa.sum(1) - pb.sum(1)).max() < 0.03
+
+
+def test_coupled_network_settles_at_its_fixed_point():
+    """Noise-free, no input, two groups of four units coupled within and
+    across groups with different strengths each way: from x = 0 every unit
+    of a group follows the same path, and the network settles where
+    x_A = a s(x_A) + c_AB s(x_B) and x_B = c_BA s(x_A) + b s(x_B) (s the
+    logistic; the fixed point of the continuous dynamics, found here by root
+    finding).  A transposed W would exchange c_AB and c_BA."""
+    from scipy.optimize import fsolve
+    a, b, c_ab, c_ba = 1.0, -0.5, 0.8, -0.6
+    nu = 8
+    Wm = np.zeros((nu, nu))
+    A, B = range(0, 4), range(4, 8)
+    for i in A:
+        for j in A:
+            if j != i:
+                Wm[i, j] = a / 3
+        for j in B:
+            Wm[i, j] = c_ab / 4
+    for i in B:
+        for j in A:
+            Wm[i, j] = c_ba / 4
+        for j in B:
+            if j != i:
+                Wm[i, j] = b / 3
+    wts = np.concatenate([Wm.ravel(), np.zeros(2 * nu)])
+    w = W.rnn(trials=2, seed=5, n_units=nu, dt=0.05, noise=0.0, thresh=1e300, input_gain=0.0,
+              max_steps=1500, n_bins=10, weights=wts)
+    out = oracle.run(w, dumps=True)
+
+    def s(x):
+        return 1.0 / (1.0 + np.exp(-x))
+
+    xa, xb = fsolve(lambda v: [v[0] - a * s(v[0]) - c_ab * s(v[1]),
+                               v[1] - c_ba * s(v[0]) - b * s(v[1])], [0.5, -0.5], xtol=1e-14)
+    swapped = fsolve(lambda v: [v[0] - a * s(v[0]) - c_ba * s(v[1]),
+                                v[1] - c_ab * s(v[0]) - b * s(v[1])], [0.5, -0.5], xtol=1e-14)
+    assert abs(swapped[0] - xa) > 0.1
+    for t in range(2):
+        x = out["run_state"][t, 2:]
+        np.testing.assert_allclose(x[:4], xa, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(x[4:], xb, rtol=0, atol=1e-9)
+    assert np.all(out["stats"][:, 2] == 2)  # undecided at the cap
