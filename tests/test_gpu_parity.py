@@ -170,3 +170,37 @@ def test_large_sweep_sampled(kind):
             np.testing.assert_allclose(g["run_state"][i], traj[-1], rtol=1e-9, atol=1e-12)
             checked += 1
     assert checked >= len(trials)
+
+
+def test_maximum_trial_count():
+    """The largest sweep of one setting the ABI takes, 2^31 - 1 trials (DDM,
+    FP64: about 2.3 x 10^11 run-steps in one lane-kernel launch, per-run
+    dumps kept on the device): the counts add up to the trial count and the
+    histogram to the decided runs, and runs at both ends of the trial range,
+    in the middle and on the last chunk boundaries match the oracle run by
+    run."""
+    import torch
+    T = 2 ** 31 - 1
+    w = W.ddm(trials=T, seed=33, n_bins=50)
+    print(f"case maximum trial count T={T}", flush=True)
+    h = cm.Handle(0)
+    ds = cm.DeviceSweep(h, w, dumps=True)
+    ds.launch()
+    torch.cuda.synchronize()
+    hist = ds.hist.cpu().numpy().view(np.uint64)
+    stats = ds.stats.cpu().numpy().view(np.uint64)
+    assert int(stats[0, 0]) + int(stats[0, 1]) + int(stats[0, 2]) == T
+    assert int(hist[0, 0].sum()) == int(stats[0, 0]) and int(hist[0, 1].sum()) == int(stats[0, 1])
+    chunk = 256 * 8  # the default shape at this size: 8 runs per lane
+    last = (T // chunk) * chunk
+    checked = 0
+    for t in sorted({0, 1, T // 2, last - 1, last, T - 2, T - 1}):
+        traj, ch, fl = oracle.trajectory(w, 0, t)
+        if fl or int(ds.run_flag[t].item()):
+            continue
+        assert int(ds.run_choice[t].item()) == ch, t
+        assert (int(ds.run_step[t].item()) & 0xFFFFFFFF) == traj.shape[0], t
+        np.testing.assert_allclose(float(ds.run_state[t, 0].item()), traj[-1][0], rtol=1e-9,
+                                   atol=1e-12)
+        checked += 1
+    assert checked >= 6
