@@ -190,8 +190,8 @@ hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
                           double* out, hipStream_t st);
-// LDS after the histogram window that the lane kernel (without time course)
-// uses to pack unfinished runs while a chunk drains.
+// LDS after the histogram window (and the time-course blocks) that the lane
+// kernel uses to pack unfinished runs while a chunk drains.
 size_t lane_stage_bytes(int kind, int precision);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 uint32_t loop_team_lanes(uint32_t J, uint64_t runs, uint32_t cus);

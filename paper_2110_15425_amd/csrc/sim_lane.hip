@@ -435,7 +435,8 @@ struct LCA {
 // workgroups [base[i], base[i+1]) belong to sweep i.
 // TC: the time-course variant, which also samples the state every
 // tc_every steps (one sweep per launch in practice; the LDS window then holds
-// each setting's time-course block after all the settings' records).
+// each setting's time-course block after all the settings' records, and the
+// drain stage follows them).
 template <class M, bool TC>
 __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
