@@ -65,7 +65,7 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "3e72b57baabdb5031b063af96eaa275a53ca02686a2816772b2bb0fbc5367c29",
+TRAFFIC = {"sources_sha256": "d7e0dc790115e2290390932e58267ad6aa4db73c685cac407c4fb6956e1b2b38",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md
            "bytes_per_launch": {6: 3315557, 8: 2826086}}

@@ -68,7 +68,7 @@ uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout (offsets in bytes from the workspace base).
 struct Layout {
-  uint64_t drive, correct, cost, wfrag, total;
+  uint64_t drive, correct, norm2, wfrag, total;
 };
 
 Layout layout(const cm_model* m, const cm_sweep* s) {
@@ -80,8 +80,8 @@ Layout layout(const cm_model* m, const cm_sweep* s) {
   if (m->kind == CM_CONFLICT_LCA) off = align_up(off + s->n_settings * 9u * 2u * sizeof(double), kWorkspaceAlign);
   if (m->kind == CM_CONFLICT_LOOP) {
     const uint64_t lv = (uint64_t)m->params[CM_LOOP_LEVELS];  // validated before any layout is used
-    L.cost = off + lv * lv * 9u * 2u * sizeof(double);  // after the drive table
-    off = align_up(L.cost + lv * lv * sizeof(double), kWorkspaceAlign);
+    L.norm2 = off + lv * lv * 9u * 2u * sizeof(double);  // after the drive table
+    off = align_up(L.norm2 + lv * lv * sizeof(double), kWorkspaceAlign);
   }
   L.wfrag = off;
   if (m->kind == CM_RATE_RNN) {
@@ -492,7 +492,7 @@ void fill_prep(const cm_model* m, const cm_sweep* s, const cm_result* r, char* w
     it.d.weights = m->weights;
     it.d.drive = (double*)(ws + L.drive);
     it.d.correct = (int32_t*)(ws + L.correct);
-    it.d.cost = (double*)(ws + L.cost);
+    it.d.norm2 = (double*)(ws + L.norm2);
     tables = 9 + it.d.n_settings * 9u;
   }
   it.end = (b.n ? b.it[b.n - 1].end : 0) + it.n_hist + it.n_stats + it.n_extra + tables;
@@ -600,7 +600,7 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   a.cost = p[CM_LOOP_COST];
   a.grid = s->grid;
   a.drive = (const double*)(ws + L.drive);
-  a.norm2 = (const double*)(ws + L.cost);
+  a.norm2 = (const double*)(ws + L.norm2);
   a.correct = (const int32_t*)(ws + L.correct);
   a.hist = r->hist;
   a.stats = r->stats;

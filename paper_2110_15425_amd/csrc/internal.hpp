@@ -85,7 +85,7 @@ struct DriveArgs {
   const double* grid;
   double* drive;     // [settings][9][2]
   int32_t* correct;  // [9]
-  double* cost;      // closed loop: [allocations] c_A^2 + c_B^2, else NULL
+  double* norm2;     // closed loop: [allocations] c_A^2 + c_B^2, else NULL
 };
 
 // Per-sweep preparation, many sweeps per launch: zero the histogram and

@@ -46,7 +46,7 @@ __device__ void write_drive(const DriveArgs& a, uint64_t i) {
     const uint32_t L = a.levels, i = (uint32_t)(s / L), k = (uint32_t)(s % L);
     cA = L == 1 ? a.amax : (a.amax * (double)i) / (double)(L - 1);
     cB = L == 1 ? a.amax : (a.amax * (double)k) / (double)(L - 1);
-    if (stim == 0) a.cost[s] = cA * cA + cB * cB;  // the allocation's squared norm, once
+    if (stim == 0) a.norm2[s] = cA * cA + cB * cB;  // the allocation's squared norm, once
   } else {
     cA = a.n_signals ? a.grid[s * a.n_signals] : 1.0;
     cB = a.n_signals ? a.grid[s * a.n_signals + 1] : 1.0;
