@@ -319,12 +319,32 @@ __global__ __launch_bounds__(kRnnBlock, 2) void rnn_f64_kernel(RnnArgs a) {
     f64x4 P[NBW];
 #pragma unroll
     for (int bw = 0; bw < NBW; ++bw) P[bw] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < NB * 4; ++kb) {
-      const double B = rt[kb][l];
+    // W's fragments come from L2: each is loaded PF K blocks ahead of its
+    // product, so that the loads' latency overlaps the products in between
+    // (one load then its product back to back waits out the whole latency).
+    constexpr int K = NB * 4, PF = 4;
+    const double* wbase = wf + (uint64_t)(w * NBW) * K * 64 + l;  // + (bw K + kb) 64
+    double Af[PF][NBW];
 #pragma unroll
-      for (int bw = 0; bw < NBW; ++bw) {
-        const double Af = wf[((uint64_t)((w * NBW + bw) * NB * 4 + kb)) * 64 + l];
-        P[bw] = __builtin_amdgcn_mfma_f64_16x16x4f64(Af, B, P[bw], 0, 0, 0);
+    for (int f = 0; f < PF; ++f)
+#pragma unroll
+      for (int bw = 0; bw < NBW; ++bw) Af[f][bw] = wbase[((uint64_t)bw * K + f) * 64];
+#pragma unroll 1
+    for (int kb0 = 0; kb0 < K; kb0 += PF) {
+#pragma unroll
+      for (int f = 0; f < PF; ++f) {
+        const int kb = kb0 + f;
+        const double B = rt[kb][l];
+        double cur[NBW];
+#pragma unroll
+        for (int bw = 0; bw < NBW; ++bw) cur[bw] = Af[f][bw];
+        // (the last PF blocks reload their own fragments: no branch in the loop)
+        const int kn = kb + PF < K ? kb + PF : kb;
+#pragma unroll
+        for (int bw = 0; bw < NBW; ++bw) Af[f][bw] = wbase[((uint64_t)bw * K + kn) * 64];
+#pragma unroll
+        for (int bw = 0; bw < NBW; ++bw)
+          P[bw] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[bw], B, P[bw], 0, 0, 0);
       }
     }
     __syncthreads();
