@@ -196,8 +196,12 @@ typedef struct {
 
 /* Pure host checks of a model/sweep pair (the rules above and the kind's
  * parameter ranges: dt > 0, noise >= 0, thresholds > 0, |start| < theta,
- * shapes); touches no device.  CM_E_INVALID or CM_E_UNSUPPORTED with the
- * reason in cm_last_error(). */
+ * shapes); touches no device.  This is the framework's sanitization check
+ * before a run (Distill, Sec. 2.2) and the type and shape extraction that
+ * follows from it (Sec. 3.1): shapes and parameters are fixed once, for the
+ * whole sweep, before any simulation work.  Every launch entry point runs
+ * the same checks first.  CM_E_INVALID or CM_E_UNSUPPORTED with the reason
+ * in cm_last_error(). */
 cm_status cm_validate(const cm_model *model, const cm_sweep *sweep);
 
 /* Workspace bytes a launch of this model/sweep needs (host only): the
@@ -211,7 +215,10 @@ cm_status cm_workspace_bytes(const cm_model *model, const cm_sweep *sweep, uint6
 
 /* A handle is bound to one HIP device (device_ordinal; CM_E_INVALID when
  * out of range) and holds that device's properties, the tuning table and
- * the serving slots; *out receives it.  Launches through a handle run on
+ * the serving slots; *out receives it.  It is the host-side state that the
+ * paper's generated code keeps between evaluations of a model (compiled
+ * once, then invoked for every grid point: Sec. 3.6, Sec. 3.7): here the
+ * launch shapes chosen for the device, never model data or results.  Launches through a handle run on
  * its device.  cm_destroy waits for work on the handle's serving slots,
  * then releases the handle; NULL is accepted.  Several threads may launch
  * through one handle while kernel timing (cm_profile) is off; the tuning
@@ -225,9 +232,19 @@ cm_status cm_destroy(cm_handle *h);
 cm_status cm_set_tuning(cm_handle *h, uint32_t kind, uint32_t precision, const cm_tuning *t);
 cm_status cm_get_tuning(cm_handle *h, uint32_t kind, uint32_t precision, cm_tuning *t);
 
-/* One sweep, stream-ordered on hip_stream (a hipStream_t, NULL = default).
- * Enqueues: output zero-fill, drive precompute (conflict LCA), the
- * simulation kernel, the score/argmax kernel when scoring is requested. */
+/* One sweep, stream-ordered on hip_stream (a hipStream_t, NULL = default):
+ * the trial loop of Sec. 2.2 (trials per setting, trial t using stimulus
+ * t mod n_stimuli, each run stepped until its end-of-trial condition or the
+ * cap) for every setting of the grid, evaluated in parallel with an
+ * independent random stream per run (Sec. 3.6), reduced to the outcome
+ * histograms modellers study (Sec. 2.1) and scored with the best allocation
+ * picked at random among ties (Sec. 2.1, Sec. 3.3).
+ * Enqueues: output zero-fill, drive precompute (conflict LCA; the
+ * loop-invariant work of Sec. 3.5), the simulation kernel, the score/argmax
+ * kernel when scoring is requested.  Errors: CM_E_INVALID for a bad
+ * argument (also a NULL handle or unaligned pointer), CM_E_BUDGET when
+ * workspace_bytes is below cm_workspace_bytes, CM_E_UNSUPPORTED for a
+ * precision the kind lacks, CM_E_DEVICE when a HIP call fails. */
 cm_status cm_launch(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
                     const cm_result *result, void *workspace, uint64_t workspace_bytes,
                     void *hip_stream);
@@ -270,9 +287,11 @@ cm_status cm_launch_timecourse(cm_handle *h, const cm_model *model, const cm_swe
  * kernels for the random numbers, the accumulator update and the threshold
  * test with compaction of the active runs, with run state in HBM and the host
  * driving the step loop (it synchronises on the stream every 16 steps to
- * stop early when no run is left).  DDM and conflict LCA only.  Results are
- * identical to cm_launch.  The workspace must hold
- * cm_unfused_workspace_bytes bytes (about 50 bytes per run). */
+ * stop early when no run is left).  DDM and conflict LCA only, at most
+ * 2^32 - 1 runs (n_settings x trials; the node kernels index runs with 32
+ * bits; CM_E_INVALID beyond).  Results are identical to cm_launch.  The
+ * workspace must hold cm_unfused_workspace_bytes bytes (about 50 bytes per
+ * run). */
 cm_status cm_unfused_workspace_bytes(const cm_model *model, const cm_sweep *sweep,
                                      uint64_t *bytes);
 cm_status cm_launch_unfused(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
@@ -353,7 +372,10 @@ cm_status cm_ceiling(cm_handle *h, const cm_model *model, uint32_t steps, uint64
 cm_status cm_profile(cm_handle *h, int enable);
 cm_status cm_profile_read(cm_handle *h, double *sim_ms, uint64_t *launches);
 
-/* Text of the last failure on this thread ("" if none). */
+/* Text of the last failure on this thread ("" if none).  The paper's
+ * generated code reports no errors of its own; this is the error channel of
+ * a C boundary that lets no exception cross it.  The pointer stays valid
+ * until the next failing call on the same thread. */
 const char *cm_last_error(void);
 
 #ifdef __cplusplus

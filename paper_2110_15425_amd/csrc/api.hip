@@ -627,8 +627,9 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
 cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm_model* ms, const cm_sweep* ss,
                             const cm_result* rs, void* const* wss, const Layout* Ls, const uint32_t* idx,
                             uint32_t n, hipStream_t stream, const TcSpec& tc = TcSpec{}) {
-  // one form per launch: the DDM scan form when every sweep of the group is
-  // small (the time course needs the lane form)
+  // one form per launch: the DDM scan form when the sweeps of the group are
+  // small (cm_launch_batch groups DDM sweeps by form; the time course needs
+  // the lane form)
   bool scan = kind == CM_DDM && !tc.every;
   for (uint32_t k = 0; k < n && scan; ++k) {
     const uint32_t i = idx[k];
@@ -960,22 +961,42 @@ cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, cons
         }
         continue;
       }
-      for (size_t g0 = 0; g0 < group.size(); g0 += cm::kMaxBatch) {
-        const size_t g1 = std::min(group.size(), g0 + (size_t)cm::kMaxBatch);
-        cm_status st = launch_lane_group(h, kind, prec, models, sweeps, results, workspaces, L.data(),
-                                         group.data() + g0, (uint32_t)(g1 - g0), stream);
-        if (st != CM_OK) return st;
+      // A DDM sweep runs in the scan form or the lane form by its own size
+      // alone (the two sum a run's increments in different orders), so the
+      // group splits by form: a sweep's states never depend on what it is
+      // batched with.
+      for (int form = 0; form < 2; ++form) {
+        std::vector<uint32_t> sub;
+        for (uint32_t i : group) {
+          const bool scan = kind == CM_DDM && scan_ddm(h->tune[kind][prec], sweeps[i].n_settings * sweeps[i].trials);
+          if ((int)scan == form) sub.push_back(i);
+        }
+        for (size_t g0 = 0; g0 < sub.size(); g0 += cm::kMaxBatch) {
+          const size_t g1 = std::min(sub.size(), g0 + (size_t)cm::kMaxBatch);
+          cm_status st = launch_lane_group(h, kind, prec, models, sweeps, results, workspaces, L.data(),
+                                           sub.data() + g0, (uint32_t)(g1 - g0), stream);
+          if (st != CM_OK) return st;
+        }
       }
     }
   return ok();
 }
 
-cm_status cm_unfused_workspace_bytes(const cm_model* m, const cm_sweep* s, uint64_t* bytes) {
-  if (!bytes) return fail(CM_E_INVALID, "bytes must not be NULL");
+// The node-by-node kernels index runs with 32-bit integers.
+static cm_status check_unfused(const cm_model* m, const cm_sweep* s) {
   cm_status st = check_model_sweep(m, s);
   if (st != CM_OK) return st;
   if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
     return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
+  if (s->n_settings * s->trials > 0xFFFFFFFFull)
+    return fail(CM_E_INVALID, "unfused execution: at most 2^32 - 1 runs (n_settings x trials)");
+  return ok();
+}
+
+cm_status cm_unfused_workspace_bytes(const cm_model* m, const cm_sweep* s, uint64_t* bytes) {
+  if (!bytes) return fail(CM_E_INVALID, "bytes must not be NULL");
+  cm_status st = check_unfused(m, s);
+  if (st != CM_OK) return st;
   *bytes = unfused_layout(m, s).total;
   return ok();
 }
@@ -983,10 +1004,8 @@ cm_status cm_unfused_workspace_bytes(const cm_model* m, const cm_sweep* s, uint6
 cm_status cm_launch_unfused(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
                             void* workspace, uint64_t workspace_bytes, void* hip_stream) {
   if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
-  cm_status st = check_model_sweep(m, s);
+  cm_status st = check_unfused(m, s);
   if (st != CM_OK) return st;
-  if (m->kind != CM_DDM && m->kind != CM_CONFLICT_LCA)
-    return fail(CM_E_UNSUPPORTED, "unfused execution: DDM and conflict LCA only");
   if ((st = check_result(m, s, r)) != CM_OK) return st;
   const UnfusedLayout U = unfused_layout(m, s);
   if (!workspace || !aligned(workspace, kWorkspaceAlign))

@@ -23,26 +23,40 @@ def refine(handle, make_workload, lo=(0.0, 0.0), hi=(5.0, 5.0), n=8, rounds=4, s
     history = []
     best_c = None
     for r in range(rounds):
-        a = np.linspace(lo[0], hi[0], n)
-        b = np.linspace(lo[1], hi[1], n)
-        A, B = np.meshgrid(a, b, indexing="ij")
-        grid = np.stack([A.ravel(), B.ravel()], 1)
+        grid = box_grid(lo, hi, n)
         w = make_workload(grid, seed + r)
         out = cm.run(w, handle=handle)
         s = int(out["best"][0])
         best_c = grid[s].copy()
         history.append(dict(round=r, lo=lo.tolist(), hi=hi.tolist(), best=best_c.tolist(),
-                            score=float(out["score"][s]), ties=int(out["best"][1]),
+                            best_index=s, score=float(out["score"][s]), ties=int(out["best"][1]),
+                            scores=out["score"].copy(), seed=seed + r,
                             runs=int(w["n_settings"] * w["trials"])))
-        step = (hi - lo) / (n - 1)
-        lo = np.maximum(lo, best_c - step)
-        hi = np.minimum(hi, best_c + step)
+        lo, hi = narrow(lo, hi, n, best_c)
     return history, best_c
 
 
-def conflict_search(trials=400, **kw):
+def box_grid(lo, hi, n):
+    """The n x n grid of allocations over the box [lo, hi] (row-major in the
+    first signal), as [n*n x 2]."""
+    a = np.linspace(lo[0], hi[0], n)
+    b = np.linspace(lo[1], hi[1], n)
+    A, B = np.meshgrid(a, b, indexing="ij")
+    return np.stack([A.ravel(), B.ravel()], 1)
+
+
+def narrow(lo, hi, n, best_c):
+    """The next round's box: one grid cell around the best allocation,
+    clipped to the current box."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    step = (hi - lo) / (n - 1)
+    return np.maximum(lo, best_c - step), np.minimum(hi, best_c + step)
+
+
+def conflict_search(trials=400, precision=W.FP32_STEP):
     """The conflict-network control search (reward 1, cost 0.1)."""
     def make(grid, seed):
         return W.conflict(trials=trials, seed=seed, grid=grid, reward=1.0, cost=0.1,
-                          precision=W.FP32_STEP)
+                          precision=precision)
     return make

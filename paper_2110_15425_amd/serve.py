@@ -125,10 +125,11 @@ class GpuBackend:
     by asynchronous copies into pinned host memory enqueued by the library
     behind the batch."""
 
-    def __init__(self, handle, n_streams=4):
+    def __init__(self, handle, n_streams=4, dumps=False):
         import torch
         self.torch = torch
         self.h = handle
+        self.dumps = dumps
         cm.serve_config(handle, n_streams)
 
     @staticmethod
@@ -136,7 +137,7 @@ class GpuBackend:
         return time.perf_counter()
 
     def launch(self, si, ws):
-        ds = [cm.DeviceSweep(self.h, w) for w in ws]
+        ds = [cm.DeviceSweep(self.h, w, dumps=self.dumps) for w in ws]
         host = [cm.host_buffers(d) for d in ds]
         ticket = cm.submit(self.h, ds, host)
         if ticket is None:  # the scheduler frees a slot only after its ticket is done
@@ -148,9 +149,12 @@ class GpuBackend:
         if not cm.poll(self.h, ticket):
             return None
         out = []
-        for hh in host:
-            out.append({k: (t.numpy().view(np.uint64) if k in ("hist", "stats") else t.numpy())
-                        for k, t in hh.items()})
+        for d, hh in zip(ds, host):
+            o = {k: (t.numpy().view(np.uint64) if k in ("hist", "stats") else t.numpy())
+                 for k, t in hh.items()}
+            if self.dumps:  # per-run dumps stay on the device; read them after the mix
+                o["device_sweep"] = d
+            out.append(o)
         return out
 
 
@@ -185,9 +189,11 @@ def served_mix(n_requests, rate_hz=50.0, seed=11, max_runs=10 ** 6, fp32=True):
     return out
 
 
-def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4):
-    """Replay a served mix in real time; returns the finished requests."""
-    be = GpuBackend(handle, n_streams)
+def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4, dumps=False):
+    """Replay a served mix in real time; returns the finished requests.  With
+    ``dumps`` every request also writes its per-run outcomes, left on the
+    device in ``result["device_sweep"]`` (its ``results()`` reads them)."""
+    be = GpuBackend(handle, n_streams, dumps=dumps)
     sch = Scheduler(be, budget_bytes, n_streams)
     t0 = be.clock()
     pending = collections.deque(Request(i, w, t0 + dt) for i, (dt, w) in enumerate(mix))

@@ -38,15 +38,60 @@ def lca_growth(w):
     return 1.0 + dt * max(0.0, comp - leak)
 
 
+# Largest amplification the difference-mode tolerance allows: 1e-13 * AMP_CAP
+# = 1e-6 absolute, about 1e-6 of the threshold.
+AMP_CAP = 1e7
+
+
+def lca_amp(w, n):
+    """Amplification of a per-step perturbation after n steps in the LCA's
+    difference mode, capped at AMP_CAP."""
+    return np.minimum(lca_growth(w) ** np.asarray(n, np.float64), AMP_CAP)
+
+
+def lca_state_check(w, g_state, o_state, n, state_rtol=1e-9, state_atol=1e-12):
+    """FP64 LCA final states, checked in the two modes of the linear update.
+
+    The update is x' = A x + dt I + b z with A = I + dt M, M = -[[leak, comp],
+    [comp, leak]].  A has the eigenvectors (1, 1) and (1, -1): the sum mode
+    x0 + x1 is multiplied by 1 - dt (leak + comp) per step (stable), the
+    difference mode x0 - x1 by g = 1 + dt (comp - leak) (g > 1 at the
+    configured leak 0.5, comp 1.0).  The two sides differ per step by a few
+    ulps of the noise increment (host and device libm round log/cos/sin
+    differently, ~1e-16 absolute), so after n steps the difference mode may
+    differ by up to ~1e-16 g^n / (g - 1): 1e-13 g^n leaves a margin of ~50.
+    That term is capped at 1e-13 * AMP_CAP = 1e-6 absolute.  The sum mode
+    gets the plain FP64 acceptance (1e-9 relative) with no amplification,
+    except with clipping at 0 (NONNEG), where clipping couples the modes and
+    both get the capped term.  Returns (max |difference|, max ratio of
+    difference to tolerance) over both modes."""
+    g_state = np.asarray(g_state, np.float64)
+    o_state = np.asarray(o_state, np.float64)
+    amp = 1e-13 * lca_amp(w, n)
+    nonneg = float(w["params"][8]) != 0.0  # the NONNEG parameter of the LCA and the loop
+    worst_d, worst_r = 0.0, 0.0
+    for name, sign in (("sum", 1.0), ("difference", -1.0)):
+        gv = g_state[:, 0] + sign * g_state[:, 1]
+        ov = o_state[:, 0] + sign * o_state[:, 1]
+        d = np.abs(gv - ov)
+        tol = state_atol + state_rtol * np.abs(ov)
+        if sign < 0 or nonneg:
+            tol = tol + amp
+        if d.size:
+            worst_d = max(worst_d, float(d.max()))
+            worst_r = max(worst_r, float((d / tol).max()))
+        bad = np.flatnonzero(d > tol)
+        assert bad.size == 0, (f"{name} mode: {bad.size} runs beyond tolerance; first {bad[:3]}: "
+                               f"diff {d[bad[:3]]} tol {tol[bad[:3]]} steps {np.asarray(n)[bad[:3]]}")
+    return worst_d, worst_r
+
+
 def assert_parity(w, g, o, correct, state_rtol=1e-9, state_atol=1e-12, max_flag_frac=1e-4):
     """FP64 acceptance: per-run integers bit-exact on runs neither side
-    flagged, final states within state_rtol, aggregate integers exact when
-    nothing is flagged (else exact after removing the flagged runs).
-
-    The two sides' normals may differ in the last bit (different libm), and
-    the LCA's difference mode amplifies such differences by lca_growth()
-    per step, so for the LCA the state tolerance grows as 1e-13 * growth^n
-    for a run of n steps (1e-13: a few hundred ulps at unit scale)."""
+    flagged, final states within state_rtol (the LCA's in its two modes, see
+    lca_state_check), aggregate integers exact when nothing is flagged (else
+    exact after removing the flagged runs).  Prints the flagged fraction and
+    the largest state difference."""
     flagged = (g["run_flag"] != 0) | (o["run_flag"] != 0)
     ok = ~flagged
     frac = flagged.mean()
@@ -56,13 +101,16 @@ def assert_parity(w, g, o, correct, state_rtol=1e-9, state_atol=1e-12, max_flag_
                            f"{g['run_choice'][bad[:5]]}/{g['run_step'][bad[:5]]} oracle "
                            f"{o['run_choice'][bad[:5]]}/{o['run_step'][bad[:5]]}")
     if int(w["kind"]) in (1, 3):  # the conflict LCA, open or closed loop
-        amp = lca_growth(w) ** o["run_step"][ok].astype(np.float64)
-        tol = np.maximum(state_atol, 1e-13 * amp)[:, None] + state_rtol * np.abs(o["run_state"][ok])
-        diff = np.abs(g["run_state"][ok] - o["run_state"][ok])
-        assert np.all(diff <= tol), f"max state excess {np.max(diff - tol)}"
+        worst_d, worst_r = lca_state_check(w, g["run_state"][ok], o["run_state"][ok],
+                                           o["run_step"][ok], state_rtol, state_atol)
     else:
-        np.testing.assert_allclose(g["run_state"][ok], o["run_state"][ok], rtol=state_rtol,
-                                   atol=state_atol)
+        gs_, os2 = g["run_state"][ok], o["run_state"][ok]
+        np.testing.assert_allclose(gs_, os2, rtol=state_rtol, atol=state_atol)
+        d = np.abs(gs_ - os2)
+        worst_d = float(d.max()) if d.size else 0.0
+        worst_r = float((d / (state_atol + state_rtol * np.abs(os2))).max()) if d.size else 0.0
+    print(f"parity: {flagged.size} runs, flagged fraction {frac:.2e}, largest state difference "
+          f"{worst_d:.3e} ({worst_r:.3f} of its tolerance)", flush=True)
     # each side's aggregates are the reduction of its own per-run outcomes
     gh, gs = reduce_dumps(w, g, correct)
     assert np.array_equal(gh, g["hist"]) and np.array_equal(gs, g["stats"])

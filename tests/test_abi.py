@@ -139,3 +139,20 @@ def test_closed_loop_validation():
     n = C.c_uint64(0)
     assert cm.lib().cm_unfused_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)) == cm.E_UNSUPPORTED
 
+
+
+def test_unfused_rejects_sweeps_beyond_32bit_run_indices():
+    """The node-by-node kernels index runs with 32 bits: sweeps of 2^32 runs
+    or more are refused (CM_E_INVALID) before anything is enqueued, up to
+    2^32 - 1 accepted."""
+    n = C.c_uint64(0)
+    big = W.ddm(trials=(1 << 31) - 1, drifts=[0.1, 0.2, 0.3])  # 3 (2^31 - 1) > 2^32
+    m, s, keep = cm.structs(big, grid_ptr=256)
+    assert cm.lib().cm_validate(C.byref(m), C.byref(s)) == cm.OK
+    assert cm.lib().cm_unfused_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)) == cm.E_INVALID
+    assert "2^32" in cm.lib().cm_last_error().decode()
+    assert cm.lib().cm_launch_unfused(None, C.byref(m), C.byref(s), None, None, 0, None) == cm.E_INVALID
+    ok = W.ddm(trials=(1 << 31) - 1, drifts=[0.1, 0.2])  # 2^32 - 2 runs
+    m, s, keep = cm.structs(ok, grid_ptr=256)
+    assert cm.lib().cm_unfused_workspace_bytes(C.byref(m), C.byref(s), C.byref(n)) == cm.OK
+    assert n.value > 0

@@ -133,6 +133,69 @@ def test_unfused_equals_fused(kind, prec):
         assert np.array_equal(got["run_state"], fused["run_state"])
 
 
+def _correct(w):
+    import oracle
+    if w["kind"] == W.DDM:
+        return [1]
+    return oracle.conflict_correct(w["weights"], w["params"][W.LCA_P["hid_gain"]],
+                                   w["params"][W.LCA_P["hid_bias"]])
+
+
+UNFUSED_ORACLE_CASES = {
+    "ddm_drifts_ragged": lambda: W.ddm(trials=3001, seed=3, drifts=np.linspace(0, 0.6, 5)),
+    "ddm_short_cap": lambda: W.ddm(trials=900, seed=8, max_steps=77, n_bins=7, noise=0.3),
+    "lca_grid_scored": lambda: W.grid_search(n=6, trials=301, seed=4),
+    "lca_nonneg": lambda: W.conflict(trials=700, seed=7, nonneg=1.0, max_steps=300, n_bins=30,
+                                     grid=W.control_grid(3)),
+    "c1_full": lambda: W.conflict(),
+}
+
+
+@pytest.mark.parametrize("name", list(UNFUSED_ORACLE_CASES))
+def test_unfused_fp64_against_oracle(name):
+    """The node-by-node kernels (their own arithmetic, state through HBM
+    every step) against the FP64 oracle: per-run integers bit-exact on
+    unflagged runs, final states within the FP64 tolerance, histograms,
+    statistics, scores and best setting equal."""
+    import oracle
+    from parity import assert_parity
+    w = UNFUSED_ORACLE_CASES[name]()
+    print(f"case unfused {name} kind={w['kind']} S={w['n_settings']} T={w['trials']}", flush=True)
+    h = cm.Handle(0)
+    ds = cm.DeviceSweep(h, w, dumps=True)
+    ds.launch_unfused()
+    g = ds.results()
+    o = oracle.run(w, dumps=True)
+    assert_parity(w, g, o, _correct(w))
+    if o["score"] is not None and not ((g["run_flag"] != 0) | (o["run_flag"] != 0)).any():
+        assert np.array_equal(g["score"], o["score"])
+        assert np.array_equal(g["best"], o["best"])
+
+
+def test_refine_fp64_against_oracle():
+    """The coarse-to-fine search in FP64 against the oracle, round by round:
+    each round's score surface and best allocation equal the oracle's on the
+    same grid and seed, and each next box is the one the oracle's best
+    allocation gives, so the whole search is the oracle's search."""
+    import oracle
+    from paper_2110_15425_amd import refine
+    h = cm.Handle(0)
+    n, rounds = 5, 3
+    make = refine.conflict_search(trials=300, precision=W.FP64)
+    hist, best = refine.refine(h, make, n=n, rounds=rounds)
+    lo, hi = np.zeros(2), np.full(2, 5.0)
+    for r in hist:
+        print(f"case refine round {r['round']} box {r['lo']} {r['hi']}", flush=True)
+        assert np.allclose(r["lo"], lo, rtol=0, atol=0) and np.allclose(r["hi"], hi, rtol=0, atol=0)
+        grid = refine.box_grid(lo, hi, n)
+        o = oracle.run(make(grid, r["seed"]))
+        assert int(o["stats"][:, 8].sum()) == 0, "flagged runs in a refinement round"
+        assert np.array_equal(r["scores"], o["score"])
+        assert r["best_index"] == int(o["best"][0]) and r["ties"] == int(o["best"][1])
+        lo, hi = refine.narrow(lo, hi, n, grid[int(o["best"][0])])
+    assert np.array_equal(best, refine.box_grid(hist[-1]["lo"], hist[-1]["hi"], n)[hist[-1]["best_index"]])
+
+
 def test_coarse_to_fine_search_matches_full_grid():
     """Four rounds of a 6x6 grid (57,600 runs) find an allocation as good as
     the best of the exhaustive 64x64 grid (409,600 runs), judged by a
@@ -230,3 +293,21 @@ def test_measured_ceiling_bounds_the_sweeps(kind, prec):
     rate = cm.run_steps(w, ds.results()) / (time.perf_counter() - t0)
     print(f"{kind} prec {prec}: ceiling {c:.3e}, sweep {rate:.3e} run-steps/s")
     assert c > rate > 0
+
+
+def test_ddm_form_independent_of_batch_partners():
+    """A small DDM sweep (wavefront-scan form) batched with one of more than
+    2^20 runs (lane form) computes bit for bit what it computes alone: the
+    batch launches each form separately."""
+    h = cm.Handle(0)
+    small = W.ddm(trials=3000, seed=2)
+    big = W.ddm(trials=(1 << 20) + 5, seed=3, max_steps=200, n_bins=10)
+    print("case ddm small + 2^20+5 batch", flush=True)
+    alone = cm.run(small, dumps=True, handle=h)
+    ds = [cm.DeviceSweep(h, small, dumps=True), cm.DeviceSweep(h, big)]
+    cm.launch_batch(h, ds)
+    got = ds[0].results()
+    for k in ("run_state", "run_choice", "run_step", "run_flag", "hist", "stats"):
+        assert np.array_equal(got[k], alone[k]), k
+    big_alone = cm.run(big, handle=h)
+    _same(ds[1].results(), big_alone)

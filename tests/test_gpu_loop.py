@@ -45,7 +45,7 @@ def test_loop_fp64_parity(name):
     o = oracle.run(w, dumps=True)
     correct = oracle.conflict_correct(w["weights"], w["params"][W.LOOP_P["hid_gain"]],
                                       w["params"][W.LOOP_P["hid_bias"]])
-    assert_parity(w, g, o, correct, max_flag_frac=1e-3)
+    assert_parity(w, g, o, correct)
 
 
 @pytest.mark.parametrize("prec", [W.FP64, W.FP32_STEP])

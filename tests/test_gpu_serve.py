@@ -92,3 +92,49 @@ def test_submit_reports_busy_slots():
         assert np.array_equal(d.results()["hist"], alone["hist"])
     with pytest.raises(cm.CmError):
         cm.poll(h, t2 + 100)
+
+
+def _correct(w):
+    import oracle
+    from paper_2110_15425_amd import workloads as W
+    if w["kind"] == W.DDM:
+        return [1]
+    if w["kind"] == W.LCA:
+        return oracle.conflict_correct(w["weights"], w["params"][W.LCA_P["hid_gain"]],
+                                       w["params"][W.LCA_P["hid_bias"]])
+    return [-1]
+
+
+def test_fp64_mix_matches_oracle():
+    """An FP64 served mix of all four configurations (16 requests arriving
+    together, overlapping on four slots, grouped into batched launches)
+    against the FP64 oracle: every request's per-run choice and decision
+    step bit-exact on unflagged runs, final states within the FP64
+    tolerance, and the served histograms, statistics, scores and best
+    setting equal to the oracle's (after removing flagged runs, if any)."""
+    import oracle
+    from parity import assert_parity
+    h = cm.Handle(0)
+    mix = serve.served_mix(16, rate_hz=1e6, seed=8, max_runs=3000, fp32=False)
+    kinds = sorted({(int(w["kind"]), float(w["reward"])) for _, w in mix})
+    assert len(kinds) == 4, kinds  # DDM, conflict LCA, scored grid, rate network
+    done = serve.run_mix(h, mix, budget_bytes=4 << 30, n_streams=4, dumps=True)
+    assert len(done) == 16
+    for r in sorted(done, key=lambda r: r.rid):
+        w = r.w
+        print(f"case served request {r.rid} kind={w['kind']} S={w['n_settings']} "
+              f"T={w['trials']}", flush=True)
+        g = dict(r.result)
+        d = g.pop("device_sweep").results()
+        for k in ("run_choice", "run_step", "run_flag", "run_state"):
+            g[k] = d[k]
+        for k in ("hist", "stats", "score", "best"):  # the host copies are the device's
+            if d[k] is not None:
+                assert np.array_equal(g[k], d[k]), k
+        o = oracle.run(w, dumps=True)
+        assert_parity(w, g, o, _correct(w))
+        if o["score"] is not None:
+            flagged = (g["run_flag"] != 0) | (o["run_flag"] != 0)
+            if not flagged.any():
+                assert np.array_equal(g["score"], o["score"])
+                assert np.array_equal(g["best"], o["best"])
