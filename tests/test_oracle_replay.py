@@ -58,3 +58,45 @@ def test_lca_replay(trial):
             assert abs(float(x[i]) - traj[n - 1, i]) <= 1e-12 * max(1.0, abs(float(x[i])))
     if not fl and ch >= 0:
         assert max(x) >= mp.mpf(0.8) and (x[1] > x[0]) == (ch == 1)
+
+
+@pytest.mark.parametrize("trial", range(2))
+def test_rnn_replay(trial):
+    """A coupled 64-unit rate network (W != 0), FP64, replayed at 50 digits
+    from the same Philox words: p = W r with W row-major (unit i receives
+    sum_j W[i][j] r_j), the Euler update of every unit, and the centred
+    readout y <- y + dt R (r - 1/2) with the rates that fed the step.  Every
+    unit and both readouts stay within 1e-11 of the oracle's FP64 trajectory
+    (its rounding only), and the decision step and choice agree."""
+    nu = 64
+    wts = W.rnn_weights(nu, 7) * 2.0  # stronger coupling than N(0, 1/n)
+    w = W.rnn(trials=2, seed=23, n_units=nu, weights=wts, max_steps=80, n_bins=10, thresh=0.25)
+    traj, ch, fl = oracle.trajectory(w, 0, trial)
+    Wm = [[mp.mpf(float(v)) for v in wts[i * nu:(i + 1) * nu]] for i in range(nu)]
+    R = [[mp.mpf(float(v)) for v in wts[nu * nu + c * nu: nu * nu + (c + 1) * nu]] for c in (0, 1)]
+    dt, noise, g = mp.mpf(0.05), mp.mpf(0.05), mp.mpf(1.0)
+    b = noise * mp.sqrt(dt)
+    u = []
+    for m in range(nu // 2):
+        u.extend(_normals(oracle.philox([m, trial, 0, 0x40000000], _key(w))))
+    x = [mp.mpf(0)] * nu
+    y = [mp.mpf(0), mp.mpf(0)]
+    half = mp.mpf(1) / 2
+    for n in range(1, traj.shape[0] + 1):
+        xi = []
+        for m in range(nu // 2):
+            xi.extend(_normals(oracle.philox([n - 1, trial, 0, m], _key(w))))
+        r = [1 / (1 + mp.exp(-v)) for v in x]
+        p = [mp.fsum(Wm[i][j] * r[j] for j in range(nu)) for i in range(nu)]
+        acc = [mp.fsum(R[c][j] * (r[j] - half) for j in range(nu)) for c in (0, 1)]
+        x = [x[i] + dt * ((p[i] - x[i]) + g * u[i]) + b * xi[i] for i in range(nu)]
+        y = [y[0] + dt * acc[0], y[1] + dt * acc[1]]
+        row = traj[n - 1]
+        assert abs(float(y[0]) - row[0]) <= 1e-11 and abs(float(y[1]) - row[1]) <= 1e-11, n
+        assert max(abs(float(x[i]) - row[2 + i]) for i in range(nu)) <= 1e-11, n
+    assert ch >= 0, "the run should decide within the cap"
+    if not fl:
+        assert max(y) >= mp.mpf(0.25) and (y[1] > y[0]) == (ch == 1)
+        if traj.shape[0] > 1:
+            prev = traj[-2]
+            assert max(prev[0], prev[1]) < 0.25
