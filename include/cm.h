@@ -249,6 +249,27 @@ cm_status cm_launch(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
                     const cm_result *result, void *workspace, uint64_t workspace_bytes,
                     void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cm_launch
+ * with the library's own scratch array as the workspace, so the caller
+ * passes only the model, sweep, outputs and stream.  The array is a static
+ * device array of CM_SCRATCH_BYTES on every device the library runs on,
+ * held until the process ends; its device address is looked up once per
+ * device by the first cm_create on it.  This call allocates nothing: no
+ * device memory, no events (cm_profile does not time it), no host heap on
+ * success.  Results equal cm_launch's for the same arguments.
+ * Errors: those of cm_launch; CM_E_BUDGET when cm_workspace_bytes of the
+ * model and sweep exceeds CM_SCRATCH_BYTES (a conflict-LCA grid of more
+ * than 29,125 settings, a closed loop of more than 166 levels).
+ * Every call on a device shares that device's one array, which keeps the
+ * last call's tables: calls that may overlap on one device (other streams,
+ * other threads, other handles) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero: each launch writes the tables
+ * it reads before reading them, on the same stream. */
+#define CM_SCRATCH_BYTES (4u << 20)
+cm_status cm_launch_scratch(cm_handle *h, const cm_model *model, const cm_sweep *sweep,
+                            const cm_result *result, void *hip_stream);
+
 /* Several sweeps in one call, stream-ordered on hip_stream.  Entry i uses
  * models[i], sweeps[i], results[i] and workspaces[i] (workspace_bytes[i]
  * bytes); every entry is validated before anything is enqueued.  Sweeps of

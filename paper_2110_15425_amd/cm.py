@@ -25,7 +25,7 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
-           "cm_get_tuning", "cm_launch", "cm_launch_batch", "cm_launch_timecourse",
+           "cm_get_tuning", "cm_launch", "cm_launch_scratch", "cm_launch_batch", "cm_launch_timecourse",
            "cm_unfused_workspace_bytes",
            "cm_launch_unfused", "cm_ddm_density", "cm_serve_config", "cm_submit", "cm_poll",
            "cm_ceiling",
@@ -87,6 +87,8 @@ def lib():
         L.cm_get_tuning.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(Tuning)]
         L.cm_launch.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.POINTER(Result),
                                 C.c_void_p, C.c_uint64, C.c_void_p]
+        L.cm_launch_scratch.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep),
+                                        C.POINTER(Result), C.c_void_p]
         L.cm_launch_batch.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
                                       C.POINTER(Result), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_uint64), C.c_void_p]
@@ -272,6 +274,14 @@ class DeviceSweep:
         check(lib().cm_launch(self.handle.h, C.byref(self.model), C.byref(self.sweep),
                               C.byref(self.result), C.c_void_p(self.workspace.data_ptr()),
                               self.workspace.numel(), C.c_void_p(st.cuda_stream)))
+
+    def launch_scratch(self, stream=None):
+        """cm_launch_scratch: the same sweep with the library's static scratch
+        array as its workspace (this object's workspace is not used)."""
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
+        check(lib().cm_launch_scratch(self.handle.h, C.byref(self.model), C.byref(self.sweep),
+                                      C.byref(self.result), C.c_void_p(st.cuda_stream)))
 
     def results(self):
         self.torch.cuda.synchronize(self.handle.device)

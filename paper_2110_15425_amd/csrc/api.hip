@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -38,9 +39,20 @@ struct cm_handle {
   uint64_t next_ticket = 1;
 };
 
+// Workspace of cm_launch_scratch: one array per device, living as long as
+// the process.  In host code `scratch` names a host-side stand-in, not the
+// device array: its device address comes from hipGetSymbolAddress (taken once
+// per device when the first handle on it is created) and only that address
+// is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CM_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of `scratch` per device ordinal (NULL until looked up).
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
 
 cm_status fail(cm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 cm_status fail(cm_status st, const char* fmt, ...) {
@@ -247,6 +259,25 @@ cm_status hip_fail(hipError_t e, const char* what) {
   return fail(CM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Look up the device address of `scratch` on device `dev`, once per device;
+// the device must be current.
+cm_status scratch_setup(int dev, int n_devices) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.size() < (size_t)n_devices) g_scratch_ptr.resize((size_t)n_devices, nullptr);
+  if (g_scratch_ptr[(size_t)dev]) return ok();
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (!p || !aligned(p, kWorkspaceAlign)) return fail(CM_E_DEVICE, "scratch array has no aligned device address");
+  g_scratch_ptr[(size_t)dev] = p;
+  return ok();
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (size_t)dev < g_scratch_ptr.size() ? g_scratch_ptr[(size_t)dev] : nullptr;
+}
+
 // Serving slots.  A busy slot becomes free once its completion event has fired.
 cm_status refresh_slot(cm_handle::Slot& sl) {
   if (!sl.busy) return CM_OK;
@@ -289,9 +320,10 @@ cm_status make_slots(cm_handle* h, uint32_t n) {
 struct ProfScope {
   cm_handle* h;
   hipStream_t st;
+  bool on = true;  // false: never time (creates no events)
   std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
   hipError_t begin() {
-    if (!h->prof) return hipSuccess;
+    if (!on || !h->prof) return hipSuccess;
     hipError_t e;
     if (h->used == h->events.size()) {
       std::pair<hipEvent_t, hipEvent_t> p{};
@@ -533,7 +565,7 @@ cm_status enqueue_score(const cm_model* m, const cm_sweep* s, const cm_result* r
 }
 
 cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
-                           char* ws, const Layout& L, hipStream_t stream) {
+                           char* ws, const Layout& L, hipStream_t stream, bool timed = true) {
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
   const uint32_t n = m->n_units;
@@ -568,7 +600,7 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
   hipError_t e;
   if ((e = cm::launch_rnn_prep(m->weights, n, ws + L.wfrag, m->precision != CM_FP64, stream)) != hipSuccess)
     return hip_fail(e, "weight fragments");
-  ProfScope prof{h, stream};
+  ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_rnn(m->precision, a, groups, stream)) != hipSuccess) return hip_fail(e, "rate-network kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -576,7 +608,7 @@ cm_status launch_rnn_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, c
 }
 
 cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
-                            char* ws, const Layout& L, hipStream_t stream) {
+                            char* ws, const Layout& L, hipStream_t stream, bool timed = true) {
   const double* p = m->params;
   cm::LoopArgs a{};
   a.trials = s->trials;
@@ -615,7 +647,7 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   const uint64_t want = (a.total_runs + teams_per_block - 1) / teams_per_block;
   const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * h->cu_count));
   hipError_t e;
-  ProfScope prof{h, stream};
+  ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_loop(m->precision, a, team, blocks, stream)) != hipSuccess)
     return hip_fail(e, "closed-loop kernel");
@@ -626,7 +658,8 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
 // One launch of the lane kernel over the sweeps idx[0..n) (same kind and precision).
 cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm_model* ms, const cm_sweep* ss,
                             const cm_result* rs, void* const* wss, const Layout* Ls, const uint32_t* idx,
-                            uint32_t n, hipStream_t stream, const TcSpec& tc = TcSpec{}) {
+                            uint32_t n, hipStream_t stream, const TcSpec& tc = TcSpec{},
+                            bool timed = true) {
   // one form per launch: the DDM scan form when the sweeps of the group are
   // small (cm_launch_batch groups DDM sweeps by form; the time course needs
   // the lane form)
@@ -667,7 +700,7 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   }
   hipError_t e;
   if ((e = cm::launch_prep(pb, stream)) != hipSuccess) return hip_fail(e, "sweep preparation");
-  ProfScope prof{h, stream};
+  ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan_block, tc.every != 0, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
@@ -705,6 +738,11 @@ cm_status cm_create(int device_ordinal, cm_handle** out) {
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device_ordinal);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  {
+    DeviceGuard guard(device_ordinal);
+    cm_status st = scratch_setup(device_ordinal, n);
+    if (st != CM_OK) return st;
+  }
   cm_handle* h = new (std::nothrow) cm_handle();
   if (!h) return fail(CM_E_DEVICE, "out of host memory");
   h->device = device_ordinal;
@@ -871,6 +909,30 @@ cm_status cm_get_tuning(cm_handle* h, uint32_t kind, uint32_t precision, cm_tuni
 cm_status cm_launch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
                     void* workspace, uint64_t workspace_bytes, void* hip_stream) {
   return cm_launch_batch(h, 1, m, s, r, &workspace, &workspace_bytes, hip_stream);
+}
+
+// cm_launch over the device's scratch array: the same kernels on one sweep,
+// with no allocation of any kind on the way (no vectors, no events).
+cm_status cm_launch_scratch(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
+                            void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  cm_status st = check_model_sweep(m, s);
+  if (st != CM_OK) return st;
+  const uint64_t need = layout(m, s).total;
+  if (need > CM_SCRATCH_BYTES)
+    return fail(CM_E_BUDGET, "sweep needs %llu workspace bytes, the scratch array holds %llu",
+                (unsigned long long)need, (unsigned long long)CM_SCRATCH_BYTES);
+  void* ws = scratch_ptr(h->device);
+  if (!ws) return fail(CM_E_DEVICE, "no scratch address for device %d", h->device);
+  Layout L;
+  st = check_launch(m, s, r, ws, CM_SCRATCH_BYTES, L);
+  if (st != CM_OK) return st;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceGuard guard(h->device);
+  if (m->kind == CM_RATE_RNN) return launch_rnn_sweep(h, m, s, r, (char*)ws, L, stream, false);
+  if (m->kind == CM_CONFLICT_LOOP) return launch_loop_sweep(h, m, s, r, (char*)ws, L, stream, false);
+  const uint32_t idx = 0;
+  return launch_lane_group(h, m->kind, m->precision, m, s, r, &ws, &L, &idx, 1, stream, TcSpec{}, false);
 }
 
 cm_status cm_launch_timecourse(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r,
