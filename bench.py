@@ -43,17 +43,17 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 # Lane-op slots of one run-step of the conflict-network LCA in the FP32-steps
 # mode: the straight-line work the method needs per step, counted from the
-# gfx950 instruction mix of the step body: Philox4x32-10 37 (the first
-# round's constant-word multiply hoisted, the last round only the two low
-# products the float normals use), Box-Muller 13 (two 24-bit uniforms, log,
-# sqrt, sin, cos on the transcendental unit, scaling), the two-unit update 10
-# (three fused multiply-adds per unit, the float-to-double conversions and
-# FP64 accumulations), the near-threshold test 4 (the float images of the new
+# gfx950 instruction mix of the step body: Philox4x32-10 35 (what depends only
+# on the run -- the round-1 product with the setting, the round-2 product with
+# the trial-dependent word -- is done once per run; the step counter enters
+# the first product as a scalar; the last round only the two low products the
+# float normals use), Box-Muller 13 (two 24-bit uniforms, log, sqrt, sin, cos
+# on the transcendental unit, scaling), the two-unit update 10 (three fused
+# multiply-adds per unit, the float-to-double conversions and FP64
+# accumulations), the near-threshold test 4 (the float images of the new
 # state, which the next step needs anyway, a max and one compare; whether any
-# lane is near is a scalar test).  Transcendentals count one slot: the step's
-# random numbers and update alone (cm_ceiling) issue at the full rate of 60
-# slots per step.
-LANE_OPS_PER_STEP = {"fp32_step": 64}
+# lane is near is a scalar test).  Transcendentals count one slot.
+LANE_OPS_PER_STEP = {"fp32_step": 62}
 
 # "FP32 batched": this many replicate sweeps (noise seeds 1..BATCH) share one
 # batched launch per benchmark step (the most one launch takes), so one

@@ -418,6 +418,10 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     a.nonneg = p[CM_LCA_NONNEG] != 0.0;
     a.drive = (const double*)(ws + L.drive);
   }
+  // the FP32 steps' constants, rounded once here as the kernels would
+  a.pf = cm::lca_f32(a.leak, a.comp, a.dt, a.b);
+  a.bf = (float)a.b;
+  a.guard_f = (float)(a.thresh - 2.0 * a.flag_eps);
   // Few runs per lane keep every SIMD busy when the launch is small (the tail
   // of long runs dominates); more runs per lane amortise the end of each
   // workgroup's chunk when the launch is large, until too few workgroups are
@@ -983,6 +987,8 @@ cm_status cm_ceiling(cm_handle* h, const cm_model* m, uint32_t steps, uint64_t l
     a.comp = p[CM_LCA_COMP];
     a.b = p[CM_LCA_NOISE] * sqrt(p[CM_LCA_DT]);
   }
+  a.pf = cm::lca_f32(a.leak, a.comp, a.dt, a.b);
+  a.bf = (float)a.b;
   DeviceGuard guard(h->device);
   const hipError_t e = cm::launch_ceiling((int)m->kind, (int)m->precision, a, steps, lanes, out,
                                           (hipStream_t)hip_stream);

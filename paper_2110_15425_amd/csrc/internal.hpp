@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/cm.h"
+#include "lca_step.hpp"
 
 namespace cm {
 
@@ -26,6 +27,9 @@ struct SimArgs {
   double thresh, flag_eps, b, dt;
   double drift, start;  // DDM
   double leak, comp;    // LCA
+  LcaF32 pf;            // LCA, FP32 steps: float(leak dt), float(comp dt), float(b)
+  float bf;             // float(b)
+  float guard_f;        // float(thresh - 2 flag_eps)
   uint32_t nonneg;
   uint32_t direct;  // 1: count finished runs straight into global memory
   uint64_t trials_magic, steps_magic;  // udiv_magic multipliers for trials and max_steps

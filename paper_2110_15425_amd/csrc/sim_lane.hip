@@ -94,10 +94,12 @@ __device__ __forceinline__ void tc_add(unsigned long long* w, double x0, double 
 // workgroup's LDS window (the time-course block after the settings' records)
 // or, in direct mode, into global memory.
 struct NoSample {
+  static constexpr bool kPerStep = false;
   __device__ __forceinline__ void operator()(Lane&, double, double) const {}
 };
 
 struct Sample {
+  static constexpr bool kPerStep = true;
   unsigned long long* base;  // [window or n_settings][K][kTcWords]
   uint32_t s_lo, every, K;
   double comp;
@@ -206,10 +208,39 @@ __device__ void flush(const SimArgs& a, const uint32_t* lds, uint32_t s_lo) {
   }
 }
 
+// The largest count not above `want` that no active lane's `left` is below:
+// the wave-uniform trip count of a step loop.  The per-lane minimum is taken
+// only when some lane is within `want` (one lane read per such lane).
+__device__ __forceinline__ uint32_t uniform_trips(uint32_t want, uint32_t left) {
+  uint32_t t = want;
+  uint64_t m = __builtin_amdgcn_ballot_w64(left < want);
+  while (m) {
+    const int l = __builtin_ctzll(m);
+    t = min(t, (uint32_t)__builtin_amdgcn_readlane((int)left, l));
+    m &= m - 1ull;
+  }
+  return t;
+}
+
+// The scalar multiple of M0 entering a block's first product, kept opaque so
+// that the product stays one multiply-add instead of a per-lane running sum.
+__device__ __forceinline__ uint64_t opaque_s(uint64_t v) {
+  asm("" : "+s"(v));
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Mechanisms.  Each model provides: begin(lane) -- set up a run; advance() --
 // execute up to `steps` steps (a step pair per random block for the DDM),
 // returning false once the run has ended; state() for dumps.
+//
+// The step loops count with a wave-uniform counter k: a run's step number is
+// its steps before the call, n0, plus k, and enters the random numbers only
+// through the first Philox product M0 (n0 + k) = M0 n0 + M0 k, whose second
+// term is a scalar.  A run's own step count is therefore written only when
+// it ends or the call returns.  When some lane is within `steps` of the cap
+// the loop also stops each lane at its own cap (a rarely taken second form
+// of the same loop).
 // ---------------------------------------------------------------------------
 
 // Drift-diffusion (Euler-Maruyama): x <- (x + a) + b z, bounds +-theta.
@@ -217,32 +248,62 @@ __device__ void flush(const SimArgs& a, const uint32_t* lds, uint32_t s_lo) {
 template <int PREC>
 struct DDM {
   double x, a_step;
+  RunKey rk;
   static constexpr int kWidth = 1;
 
-  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L) {
+  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1) {
     const double drift = A.n_signals ? A.grid[(uint64_t)L.s * A.n_signals] : A.drift;
     a_step = drift * A.dt;
     x = A.start;
     L.target = 1;  // the upper boundary is the correct response
+    rk = run_key(L.t, L.s, k0, k1);
   }
 
-  // guard = thresh - 2 eps: nearer the origin no bound is within flag distance
+  // One step from normal z (zf in FP32 steps); false once the run has ended
+  // (L.n is then its decision step n).  guard = thresh - 2 eps: nearer the
+  // origin no bound is within flag distance.
   template <class H>
-  __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, double z, float zf, float af,
-                                      float bf, double guard, const H& hook) {
+  __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, uint32_t n, double z, float zf,
+                                      float af, double guard, const H& hook) {
     if (PREC == CM_FP64) x = (x + a_step) + A.b * z;
-    else x = x + (double)fmaf(bf, zf, af);
-    L.n += 1;
-    hook(L, x, 0.0);
+    else x = x + (double)fmaf(A.bf, zf, af);
+    if constexpr (H::kPerStep) {
+      L.n = n;
+      hook(L, x, 0.0);
+    }
     // one comparison per step; the exact tests run only within 2 eps of a
     // bound (the whole wavefront takes the branch when any lane is near; the
     // exact tests are false for the others)
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(fabs(x) >= guard) != 0, 0)) {
       const double th = A.thresh;
       if (near_th(x, th, A.flag_eps) || near_th(x, -th, A.flag_eps)) L.flag = true;
-      if (x >= th) { L.choice = 1; return false; }
-      if (x <= -th) { L.choice = 0; return false; }
+      if (x >= th) { L.choice = 1; L.n = n; return false; }
+      if (x <= -th) { L.choice = 0; L.n = n; return false; }
     }
+    return true;
+  }
+
+  // `pairs` step pairs (wave-uniform), every active lane having at least
+  // that many whole pairs left before the cap.
+  template <class H>
+  __device__ __forceinline__ bool pairs_loop(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                             uint32_t pairs, const H& hook) {
+    const float af = (float)a_step;
+    const double guard = A.thresh - 2.0 * A.flag_eps;
+    const uint32_t n0 = L.n, b0 = n0 >> 1;  // a running lane enters at an even step count
+    uint64_t kM = 0;
+    for (uint32_t p = 0; p < pairs; ++p) {
+      const Words w = philox_run(b0, opaque_s(kM), rk, k0, k1);
+      double z0 = 0, z1 = 0;
+      float f0 = 0, f1 = 0;
+      if (PREC == CM_FP64) normals64(w, z0, z1);
+      else normals32(w, f0, f1);
+      const uint32_t n = n0 + 2u * p;
+      if (!one(A, L, n + 1u, z0, f0, af, guard, hook)) return false;
+      if (!one(A, L, n + 2u, z1, f1, af, guard, hook)) return false;
+      kM += kPhiloxM0;
+    }
+    L.n = n0 + 2u * pairs;
     return true;
   }
 
@@ -252,25 +313,17 @@ struct DDM {
   template <class H>
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int pairs, const H& hook) {
-    const float af = (float)a_step, bf = (float)A.b;
-    const double guard = A.thresh - 2.0 * A.flag_eps;
-    const uint32_t full = min((uint32_t)pairs, (A.max_steps - L.n) >> 1);
-    for (uint32_t p = 0; p < full; ++p) {
-      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
+    const uint32_t t = uniform_trips((uint32_t)pairs, (A.max_steps - L.n) >> 1);
+    if (!pairs_loop(A, L, k0, k1, t, hook)) return false;
+    if (L.n + 1u == A.max_steps) {  // an odd cap's own step, first of a pair
+      const Words w = philox_run(L.n >> 1, 0ull, rk, k0, k1);
       double z0 = 0, z1 = 0;
       float f0 = 0, f1 = 0;
       if (PREC == CM_FP64) normals64(w, z0, z1);
       else normals32(w, f0, f1);
-      if (!one(A, L, z0, f0, af, bf, guard, hook)) return false;
-      if (!one(A, L, z1, f1, af, bf, guard, hook)) return false;
-    }
-    if (full < (uint32_t)pairs && L.n < A.max_steps) {  // the cap's own step, first of a pair
-      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
-      double z0 = 0, z1 = 0;
-      float f0 = 0, f1 = 0;
-      if (PREC == CM_FP64) normals64(w, z0, z1);
-      else normals32(w, f0, f1);
-      if (!one(A, L, z0, f0, af, bf, guard, hook)) return false;
+      const uint32_t n = L.n + 1u;
+      if (!one(A, L, n, z0, f0, (float)a_step, A.thresh - 2.0 * A.flag_eps, hook)) return false;
+      L.n = n;
     }
     if (L.n == A.max_steps) {  // the cap, reached without a crossing
       L.choice = -1;
@@ -283,15 +336,19 @@ struct DDM {
 
   // Ceiling measurement: the random numbers and updates of `steps` steps
   // (rounded up to pairs) with no tests, exits or bookkeeping.
-  __device__ __forceinline__ void free_init(const SimArgs& A) {
+  __device__ __forceinline__ void free_init(const SimArgs& A, const Lane& L, uint32_t k0, uint32_t k1) {
     a_step = A.drift * A.dt;
     x = A.start;
+    rk = run_key(L.t, L.s, k0, k1);
   }
   __device__ __forceinline__ void free_steps(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                              uint32_t steps) {
-    const float af = (float)a_step, bf = (float)A.b;
+    const float af = (float)a_step;
+    const uint32_t b0 = L.n >> 1;
+    uint64_t kM = 0;
     for (uint32_t p = 0; p < (steps + 1u) / 2u; ++p) {
-      const Words w = philox(L.n >> 1, L.t, L.s, 0u, k0, k1);
+      const Words w = philox_run(b0, opaque_s(kM), rk, k0, k1);
+      kM += kPhiloxM0;
       if (PREC == CM_FP64) {
         double z0, z1;
         normals64(w, z0, z1);
@@ -300,91 +357,125 @@ struct DDM {
       } else {
         float f0, f1;
         normals32(w, f0, f1);
-        x = x + (double)fmaf(bf, f0, af);
-        x = x + (double)fmaf(bf, f1, af);
+        x = x + (double)fmaf(A.bf, f0, af);
+        x = x + (double)fmaf(A.bf, f1, af);
       }
-      L.n += 2;
     }
+    L.n += 2u * ((steps + 1u) / 2u);
   }
 };
 
 // Two-unit leaky competing accumulator with simultaneous update:
-// x_i <- x_i + ((I_i - leak x_i - comp x_j) dt) + b z_i.
+// x_i <- x_i + ((I_i - leak x_i - comp x_j) dt) + b z_i.  The run's drive:
+// I_i in double (FP64), float(I_i dt) in FP32 steps.
+struct LcaDrive64 {
+  double in0, in1;
+};
+struct LcaDrive32 {
+  float idt0, idt1;
+};
+
 template <int PREC>
-struct LCA {
-  double x0, x1, in0, in1;
-  float idt0, idt1;  // FP32 steps: float(I_i dt)
+struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
+  double x0, x1;
+  RunKey rk;
   static constexpr int kWidth = 2;
 
-  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L) {
+  __device__ __forceinline__ void begin(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1) {
     const uint32_t stim = L.t % 9u;
     const double* d = A.drive + ((uint64_t)L.s * 9u + stim) * 2u;
-    in0 = d[0];
-    in1 = d[1];
-    idt0 = (float)(in0 * A.dt);
-    idt1 = (float)(in1 * A.dt);
+    if constexpr (PREC == CM_FP64) {
+      this->in0 = d[0];
+      this->in1 = d[1];
+    } else {
+      this->idt0 = (float)(d[0] * A.dt);
+      this->idt1 = (float)(d[1] * A.dt);
+    }
     x0 = 0.0;
     x1 = 0.0;
     L.target = A.correct[stim];
+    rk = run_key(L.t, L.s, k0, k1);
+  }
+
+  // One step from the block w; false once the run has ended (L.n is then its
+  // decision step n).  xf0, xf1: the float images of the state (FP32 steps).
+  template <class H>
+  __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, uint32_t n, const Words& w,
+                                      float& xf0, float& xf1, const H& hook) {
+    double y0, y1;
+    if constexpr (PREC == CM_FP64) {
+      double z0, z1;
+      normals64(w, z0, z1);
+      y0 = (x0 + (((this->in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
+      y1 = (x1 + (((this->in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
+    } else {
+      float z0, z1;
+      normals32(w, z0, z1);
+      y0 = x0 + (double)lca_inc_f32(A.pf, this->idt0, xf0, xf1, z0);
+      y1 = x1 + (double)lca_inc_f32(A.pf, this->idt1, xf1, xf0, z1);
+    }
+    if (A.nonneg) {
+      if (y0 < 0.0) y0 = 0.0;
+      if (y1 < 0.0) y1 = 0.0;
+    }
+    x0 = y0;
+    x1 = y1;
+    if constexpr (H::kPerStep) {
+      L.n = n;
+      hook(L, x0, x1);
+    }
+    // cheap comparisons per step; the exact tests run only within 2 eps of
+    // the threshold, where a unit can be within flag distance or across.
+    // FP32 steps compare the float images of the new state (which the next
+    // step needs anyway) with the float image of the guard: rounding is
+    // monotone, so x >= guard implies float(x) >= float(guard).  The whole
+    // wavefront takes the branch when any lane is near (the exact tests
+    // are false for the others), so the test needs no per-lane mask.
+    const double th = A.thresh, eps = A.flag_eps;
+    bool near;
+    if constexpr (PREC == CM_FP64) {
+      near = (x0 > x1 ? x0 : x1) >= th - 2.0 * eps;
+    } else {
+      xf0 = (float)x0;
+      xf1 = (float)x1;
+      near = (xf0 >= A.guard_f) | (xf1 >= A.guard_f);
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(near) != 0, 0)) {
+      if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+      const double mx = x0 > x1 ? x0 : x1;
+      if (mx >= th) {
+        L.choice = (x1 > x0) ? 1 : 0;
+        if (fabs(x0 - x1) < eps) L.flag = true;
+        L.n = n;
+        return false;
+      }
+    }
+    return true;
+  }
+
+  // `steps` steps (wave-uniform), every active lane having at least that
+  // many left before the cap.
+  template <class H>
+  __device__ __forceinline__ bool steps_loop(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
+                                             uint32_t steps, const H& hook) {
+    const uint32_t n0 = L.n;
+    float xf0 = (float)x0, xf1 = (float)x1;
+    uint64_t kM = 0;
+    for (uint32_t k = 0; k < steps; ++k) {
+      const Words w = philox_run(n0, opaque_s(kM), rk, k0, k1);
+      if (!one(A, L, n0 + k + 1u, w, xf0, xf1, hook)) return false;
+      kM += kPhiloxM0;
+    }
+    L.n = n0 + steps;
+    return true;
   }
 
   template <class H>
   __device__ __forceinline__ bool advance(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                           int steps, const H& hook) {
-    const double th = A.thresh, eps = A.flag_eps, guard = th - 2.0 * eps;
-    // the step cap bounds the loop, so the body needs no cap test
-    const uint32_t lim = min((uint32_t)steps, A.max_steps - L.n);
-    // FP32 steps: the float images of the state, carried from step to step
-    float xf0 = (float)x0, xf1 = (float)x1;
-    const float gf = (float)guard;
-    const LcaF32 pf = lca_f32(A.leak, A.comp, A.dt, A.b);
-    for (uint32_t k = 0; k < lim; ++k) {
-      const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
-      double y0, y1;
-      if (PREC == CM_FP64) {
-        double z0, z1;
-        normals64(w, z0, z1);
-        y0 = (x0 + (((in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
-        y1 = (x1 + (((in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
-      } else {
-        float z0, z1;
-        normals32(w, z0, z1);
-        y0 = x0 + (double)lca_inc_f32(pf, idt0, xf0, xf1, z0);
-        y1 = x1 + (double)lca_inc_f32(pf, idt1, xf1, xf0, z1);
-      }
-      if (A.nonneg) {
-        if (y0 < 0.0) y0 = 0.0;
-        if (y1 < 0.0) y1 = 0.0;
-      }
-      x0 = y0;
-      x1 = y1;
-      L.n += 1;
-      hook(L, x0, x1);
-      // cheap comparisons per step; the exact tests run only within 2 eps of
-      // the threshold, where a unit can be within flag distance or across.
-      // FP32 steps compare the float images of the new state (which the next
-      // step needs anyway) with the float image of the guard: rounding is
-      // monotone, so x >= guard implies float(x) >= float(guard).  The whole
-      // wavefront takes the branch when any lane is near (the exact tests
-      // are false for the others), so the test needs no per-lane mask.
-      bool near;
-      if (PREC == CM_FP64) {
-        near = (x0 > x1 ? x0 : x1) >= guard;
-      } else {
-        xf0 = (float)x0;
-        xf1 = (float)x1;
-        near = (xf0 >= gf) | (xf1 >= gf);
-      }
-      if (__builtin_expect(__builtin_amdgcn_ballot_w64(near) != 0, 0)) {
-        if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
-        const double mx = x0 > x1 ? x0 : x1;
-        if (mx >= th) {
-          L.choice = (x1 > x0) ? 1 : 0;
-          if (fabs(x0 - x1) < eps) L.flag = true;
-          return false;
-        }
-      }
-    }
+    // the step cap bounds the trip count, so the body needs no cap test
+    const uint32_t t = uniform_trips((uint32_t)steps, A.max_steps - L.n);
+    if (!steps_loop(A, L, k0, k1, t, hook)) return false;
     if (L.n == A.max_steps) {  // the cap, reached without a crossing
       L.choice = -1;
       return false;
@@ -399,35 +490,43 @@ struct LCA {
 
   // Ceiling measurement: the random numbers and updates of `steps` steps
   // with no tests, exits or bookkeeping (fixed drive).
-  __device__ __forceinline__ void free_init(const SimArgs& A) {
-    in0 = 0.3;
-    in1 = 0.2;
-    idt0 = (float)(in0 * A.dt);
-    idt1 = (float)(in1 * A.dt);
+  __device__ __forceinline__ void free_init(const SimArgs& A, const Lane& L, uint32_t k0, uint32_t k1) {
+    if constexpr (PREC == CM_FP64) {
+      this->in0 = 0.3;
+      this->in1 = 0.2;
+    } else {
+      this->idt0 = (float)(0.3 * A.dt);
+      this->idt1 = (float)(0.2 * A.dt);
+    }
     x0 = 0.0;
     x1 = 0.0;
+    rk = run_key(L.t, L.s, k0, k1);
   }
   __device__ __forceinline__ void free_steps(const SimArgs& A, Lane& L, uint32_t k0, uint32_t k1,
                                              uint32_t steps) {
+    float xf0 = 0.0f, xf1 = 0.0f;
+    const uint32_t n0 = L.n;
+    uint64_t kM = 0;
     for (uint32_t k = 0; k < steps; ++k) {
-      const Words w = philox(L.n, L.t, L.s, 0u, k0, k1);
-      if (PREC == CM_FP64) {
+      const Words w = philox_run(n0, opaque_s(kM), rk, k0, k1);
+      kM += kPhiloxM0;
+      if constexpr (PREC == CM_FP64) {
         double z0, z1;
         normals64(w, z0, z1);
-        const double y0 = (x0 + (((in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
-        const double y1 = (x1 + (((in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
+        const double y0 = (x0 + (((this->in0 - A.leak * x0) - A.comp * x1) * A.dt)) + A.b * z0;
+        const double y1 = (x1 + (((this->in1 - A.leak * x1) - A.comp * x0) * A.dt)) + A.b * z1;
         x0 = y0;
         x1 = y1;
       } else {
         float z0, z1;
         normals32(w, z0, z1);
-        const LcaF32 pf = lca_f32(A.leak, A.comp, A.dt, A.b);
-        const float xf0 = (float)x0, xf1 = (float)x1;
-        x0 = x0 + (double)lca_inc_f32(pf, idt0, xf0, xf1, z0);
-        x1 = x1 + (double)lca_inc_f32(pf, idt1, xf1, xf0, z1);
+        x0 = x0 + (double)lca_inc_f32(A.pf, this->idt0, xf0, xf1, z0);
+        x1 = x1 + (double)lca_inc_f32(A.pf, this->idt1, xf1, xf0, z1);
+        xf0 = (float)x0;
+        xf1 = (float)x1;
       }
-      L.n += 1;
     }
+    L.n = n0 + steps;
   }
 };
 
@@ -484,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
     L.flag = false;
     L.next_sample = a.tc_every;
     L.sample_k = 0;
-    m.begin(a, L);
+    m.begin(a, L, k0, k1);
   };
   if (have) setup(off);
 
@@ -608,12 +707,14 @@ __global__ __launch_bounds__(kScanBlockMax) void ddm_scan_kernel(LaneBatch batch
     L.n = N;
     const double drift = a.n_signals ? a.grid[(uint64_t)L.s * a.n_signals] : a.drift;
     const double as = drift * a.dt;
-    const float af = (float)as, bf = (float)a.b;
+    const float af = (float)as, bf = a.bf;
+    const RunKey rk = run_key(L.t, L.s, k0, k1);
     double xs = a.start;  // state before the block
     uint32_t n0 = 0;      // steps executed before the block
     for (;;) {
       const uint32_t s1 = n0 + 2u * (uint32_t)lane + 1u, s2 = s1 + 1u;  // this lane's steps
-      const Words w = philox((n0 >> 1) + (uint32_t)lane, L.t, L.s, 0u, k0, k1);
+      // block (n0 / 2) + lane: the wave's common part enters as a scalar
+      const Words w = philox_run((uint32_t)lane, (uint64_t)kPhiloxM0 * (n0 >> 1), rk, k0, k1);
       double d1, d2;
       if (PREC == CM_FP64) {
         double z0, z1;
@@ -682,9 +783,9 @@ __global__ __launch_bounds__(kBlock) void ceiling_kernel(SimArgs a, uint32_t ste
   Lane L{};
   L.s = 0;
   L.t = (uint32_t)g;
-  L.n = 0;
+  L.n = 2u * ((uint32_t)g & 255u);  // lanes of a sweep are at different steps
   M m;
-  m.free_init(a);
+  m.free_init(a, L, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
   m.free_steps(a, L, (uint32_t)a.seed, (uint32_t)(a.seed >> 32), steps);
   double st[M::kWidth];
   m.state(st);
