@@ -98,6 +98,8 @@ def _side(name):
         "c3_bf16": (W.rnn(precision=W.BF16_PROJ), "launch"),
         "c3_fp64": (W.rnn(), "launch"),
         "density_c0_64drifts": (W.ddm(drifts=[0.3 * (i + 1) / 64 for i in range(64)]), "density"),
+        "density_c0_256drifts": (W.ddm(drifts=[0.3 * (i + 1) / 256 for i in range(256)]),
+                                 "density"),
         "timecourse_c1_fp32": (W.conflict(precision=f32), "timecourse"),
         "loop_l8_m4_fp32": (W.control_loop(trials=20_000, costs=[0.0, 0.003, 0.01, 0.03],
                                            precision=f32), "launch"),
@@ -111,6 +113,7 @@ def _side(name):
 
 SIDE_WORKLOADS = ("c0_fp64", "c0_fp32", "c0x1000_fp64", "c0x1000_fp32", "c1_fp64", "c1_fp32",
                   "c2_fp32", "c2_fp64", "c3_bf16", "c3_fp64", "density_c0_64drifts",
+                  "density_c0_256drifts",
                   "timecourse_c1_fp32", "loop_l8_m4_fp32", "loop_l100_m1_fp32",
                   "unfused_c1_fp32")
 

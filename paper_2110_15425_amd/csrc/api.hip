@@ -1176,11 +1176,7 @@ cm_status cm_ddm_density(cm_handle* h, const cm_model* m, const cm_sweep* s, uin
   a.tol = tol;
   a.grid = s->grid;
   a.out = first_passage;
-  // as many source-splitting thread groups as the workgroup size and LDS allow
-  const uint32_t tpq = cm::density_threads_per_split(n_cells);
-  a.splits = std::min<uint32_t>(8, 1024u / tpq);
-  while (a.splits > 1 && cm::density_lds_bytes(n_cells, a.splits) > h->lds_per_block) --a.splits;
-  if (cm::density_lds_bytes(n_cells, a.splits) > h->lds_per_block)
+  if (cm::density_lds_bytes(n_cells) > h->lds_per_block)
     return fail(CM_E_INVALID, "n_cells %u needs more LDS than a workgroup has", n_cells);
   DeviceGuard guard(h->device);
   hipStream_t stream = (hipStream_t)hip_stream;

@@ -6,20 +6,35 @@
 // model executions (Sec. 1, Sec. 4.4).  For the Euler-Maruyama walk
 // x_n = x_{n-1} + a + b z_n with absorbing bounds +-theta, the survivor mass
 // on M cells of (-theta, theta) evolves by a Gaussian transition kernel: the
-// mass moving from cell i to cell j depends only on j - i (a convolution),
-// and the mass absorbed at either bound from cell i is a Gaussian tail.  The
-// first step leaves the exact start point; later steps leave cell centres
-// (midpoint rule, error O(h^2)).  One workgroup per setting keeps the kernel
-// row and the mass vectors in LDS for all steps; up to eight groups of
-// threads split the source cells of each step and add their partial sums.
+// mass moving from cell i to cell j depends only on j - i (a Toeplitz
+// matrix T), and the mass absorbed at either bound from cell i is a Gaussian
+// tail.  The first step leaves the exact start point; later steps leave cell
+// centres (midpoint rule, error O(h^2)).
+//
+// One workgroup per setting keeps the kernel row and the mass vectors in LDS
+// for all steps.  The product T m is a dense contraction on the FP64 matrix
+// cores: with cells grouped in blocks of 16, block-diagonal d of T is one
+// 16x16 matrix F_d (F_d[alpha][gamma] = f(16 d + alpha - gamma)), so
+//   y_block(a) = sum_d F_d m_block(a - d),
+// i.e. for every d a 16x16 by 16 x (blocks) product.  Each 16x16x4 product
+// takes its F_d fragment straight from the kernel row in LDS and its mass
+// fragment from the (zero-padded) mass vector.  Block-diagonals whose
+// entries are all below 2^-60 (the Gaussian's far tails, at most 2^-60 of a
+// row's mass each) are skipped, as are blocks whose mass columns lie outside
+// the grid.  Wavefront (tile t, group g) accumulates the output columns
+// 16 t .. 16 t + 15 over its share (the g-th of G contiguous ranges) of the
+// block-diagonals; the groups' partial sums are added in group order
+// through LDS.
 #include "internal.hpp"
 
 namespace cm {
 namespace {
 
-constexpr int kOut = 8;       // consecutive output cells per thread
-constexpr int kFPad = 16;     // zero cells in front of the kernel row
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kMaxThreads = 1024;
+constexpr int kBS = 17;  // LDS slots per 16-cell block of a mass vector (one pad)
+constexpr int kWin = 16; // steps whose sums are reduced together
 
 __device__ __forceinline__ double Phi(double x) { return 0.5 * erfc(-x * 0.70710678118654752440); }
 
@@ -52,225 +67,283 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// LDS position of kernel-row entry x (x >= -kFPad), u = x + kFPad: one pad
-// slot after every 8 entries.  Threads own 8 consecutive output cells, so
-// within a wavefront their reads of the row are 8 entries, i.e. 9 slots (18
-// banks) apart: no two of them share a bank.  The 8 entries 8m..8m+7 sit
-// contiguously at 9m..9m+7, which lets the source loop read them as a group.
-__device__ __forceinline__ uint32_t fpos_u(uint32_t u) { return u + (u >> 3); }
-__device__ __forceinline__ uint32_t fpos(int x) { return fpos_u((uint32_t)(x + kFPad)); }
+// Sum over the 16-lane row, the same value in every lane of the row.
+__device__ __forceinline__ double row_sum(double v) {
+  v += partner<0>(v);
+  v += partner<1>(v);
+  v += partner<2>(v);
+  v += partner<3>(v);
+  return v;
+}
 
-// Logical and LDS sizes of the row: 2M - 1 entries after kFPad zeros, and up
-// to 8 past them read by the windows of output cells beyond M.
-__host__ __device__ inline uint32_t frow_entries(uint32_t M) { return ((2u * M + kFPad + 8u + 7u) / 8u) * 8u; }
-__host__ __device__ inline uint32_t frow_slots(uint32_t M) { return frow_entries(M) / 8u * 9u; }
-// Rows of the split groups' partial sums use the same padding (cell j at
-// j + j/8), so that threads writing 8 consecutive cells do not collide.
-__host__ __device__ inline uint32_t prow_slots(uint32_t M) { return (M + M / 8u + 2u) & ~1u; }
+__device__ __forceinline__ int floor_div16(int v) { return v >= 0 ? v / 16 : -((15 - v) / 16); }
+__device__ __forceinline__ int ceil_div16(int v) { return -floor_div16(-v); }
 
-// Launch geometry, computed on the host: Q thread groups split the source
-// cells of each step, each group has TPQ threads (a multiple of 64 covering
-// the ceil(M/8) output blocks), block = Q * TPQ.
+}  // namespace
+
+// Launch geometry of M cells: NB blocks of 16 cells, NT output tiles of 16
+// blocks, G wavefronts per tile (W = NT G, 8 to 12; measured on MI355X at
+// 1000 cells: 2 per tile 5 % faster than 4, 1 per tile 25 % slower), the
+// kernel row's offset
+// FOFF (entry of displacement 0) and width FW, and CB blocks per mass vector
+// (NB zero blocks on either side of the 16 NT output blocks).
+struct DensityGeo {
+  uint32_t M, NB, NT, G, W, FOFF, FW, CB;
+};
+__host__ __device__ inline DensityGeo density_geo(uint32_t M) {
+  DensityGeo g;
+  g.M = M;
+  g.NB = (M + 15u) / 16u;
+  g.NT = (g.NB + 15u) / 16u;
+  g.G = 8u / g.NT > 2u ? 8u / g.NT : 2u;
+  g.W = g.NT * g.G;
+  g.FOFF = 16u * g.NB + 16u;
+  g.FW = 2u * g.FOFF + 1u;
+  g.CB = 16u * g.NT + 2u * g.NB;
+  return g;
+}
+
+namespace {
+
 __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a) {
   extern __shared__ double sh[];
-  __shared__ double red[2][kMaxThreads / 64];
-  __shared__ double red_sv[kMaxThreads / 64];
-  const uint32_t M = a.cells, tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t Q = a.splits, TPQ = nt / Q, q = tid / TPQ, blk = tid - q * TPQ;
-  const uint32_t nb = (M + kOut - 1) / kOut;
-  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  const uint32_t fsize = frow_entries(M);
-  double* f = sh;                   // kernel row at fpos, [frow_slots]
-  double* m0 = f + frow_slots(M);   // mass vectors [M]
-  double* m1 = m0 + M;
-  double* part = m1 + M;     // partial sums of the Q splits, [Q][prow_slots]
-  const uint32_t PM = prow_slots(M);
-  double* upc = part + Q * PM;  // per cell: mass absorbed at the upper bound in one step
-  double* loc = upc + M;        // and at the lower bound
+  __shared__ double red[3][kMaxThreads / 64];
+  __shared__ double wsum[3][kWin];
+  __shared__ int band[2];
+  const DensityGeo geo = density_geo(a.cells);
+  const uint32_t M = geo.M, NB = geo.NB, NT = geo.NT, G = geo.G;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const int lane = (int)(tid & 63u), wave = (int)(tid >> 6), nw = (int)(nt >> 6);
+  double* f = sh;                       // kernel row: f[FOFF + delta], [FW]
+  double* m0 = f + geo.FW;              // mass vectors, block c at (c + NB) * kBS
+  double* m1 = m0 + geo.CB * kBS;
+  double* part = m1 + geo.CB * kBS;     // partial sums [G][NT][4][64]
+  // per step of a window: the 16-lane rows' sums of the new mass, and of the
+  // mass the next step absorbs at either bound, [kWin][3][rows]
+  double* ring = part + G * NT * 256u;
   const uint64_t s = blockIdx.x;
   const double drift = a.n_signals ? a.grid[s * a.n_signals] : a.drift;
   const double as = drift * a.dt, b = a.b, th = a.thresh, h = (2.0 * th) / (double)M;
   double* out_lo = a.out + (s * 2u) * a.max_steps;  // choice 0: lower bound
   double* out_up = out_lo + a.max_steps;             // choice 1: upper bound
 
-  // kernel row: entry x = d + (M - 1) is the mass moving d cells up
-  for (uint32_t u = tid; u < fsize; u += nt) {
-    const int x = (int)u - kFPad;
+  if (tid == 0) {
+    band[0] = 0x7FFFFFFF;
+    band[1] = -0x7FFFFFFF;
+  }
+  for (uint32_t i = tid; i < 2u * geo.CB * kBS; i += nt) m0[i] = 0.0;
+  __syncthreads();
+  // kernel row: entry delta is the mass moving delta cells up; the band of
+  // displacements whose entries reach 2^-60
+  for (uint32_t x = tid; x < geo.FW; x += nt) {
+    const int d = (int)x - (int)geo.FOFF;
     double v = 0.0;
-    if (x >= 0 && x < (int)(2 * M - 1)) {
-      const double k = (double)(x - (int)(M - 1));
+    if (d > -(int)M && d < (int)M) {
+      const double k = (double)d;
       v = Phi(((k + 0.5) * h - as) / b) - Phi(((k - 0.5) * h - as) / b);
     }
-    f[fpos_u(u)] = v;
+    f[x] = v;
+    if (v >= 0x1p-60) {
+      atomicMin(&band[0], d);
+      atomicMax(&band[1], d);
+    }
   }
-  // absorption tables (in LDS, so that the registers hold the convolution's
-  // window and sums)
-  for (uint32_t i = tid; i < M; i += nt) {
-    const double c = -th + ((double)i + 0.5) * h;
-    upc[i] = Phi(-((th - c) - as) / b);
-    loc[i] = Phi(((-th - c) - as) / b);
-    // first step from the start point, exact
-    const double x0 = a.start;
-    const double e0 = -th + (double)i * h, e1 = -th + (double)(i + 1) * h;
-    m0[i] = Phi(((e1 - x0) - as) / b) - Phi(((e0 - x0) - as) / b);
+  // This thread's output slots: slot t is register r of lane l of tile tt's
+  // accumulator, cell 16 (16 tt + l % 16) + 4 r + l / 16 (the 16x16x4 FP64
+  // accumulator holds row 4 r + l / 16, column l % 16).  Their absorption
+  // tables stay in registers; the first step's mass comes from the start
+  // point exactly.
+  constexpr int kSlots = 2;
+  double upc[kSlots], loc[kSlots];
+  uint32_t pos[kSlots];
+  bool real[kSlots];
+  double pu = 0.0, pl = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const uint32_t t = tid + (uint32_t)k * nt;
+    const uint32_t tt = t >> 8, r = (t >> 6) & 3u, l = t & 63u;
+    const uint32_t blk = 16u * tt + (l & 15u), j = 16u * blk + 4u * r + (l >> 4);
+    real[k] = t < 256u * NT && j < M;
+    pos[k] = (blk + NB) * kBS + 4u * r + (l >> 4);
+    upc[k] = loc[k] = 0.0;
+    if (real[k]) {
+      const double c = -th + ((double)j + 0.5) * h;
+      upc[k] = Phi(-((th - c) - as) / b);
+      loc[k] = Phi(((-th - c) - as) / b);
+      const double e0 = -th + (double)j * h, e1 = -th + (double)(j + 1) * h;
+      const double v = Phi(((e1 - a.start) - as) / b) - Phi(((e0 - a.start) - as) / b);
+      m0[pos[k]] = v;
+      pu = fma(v, upc[k], pu);
+      pl = fma(v, loc[k], pl);
+    }
   }
+  pu = wave_sum(pu);
+  pl = wave_sum(pl);
+  if (lane == 0) {
+    red[1][wave] = pu;
+    red[2][wave] = pl;
+  }
+  __syncthreads();
   if (tid == 0) {
     out_up[0] = Phi(-((th - a.start) - as) / b);
     out_lo[0] = Phi(((-th - a.start) - as) / b);
+    if (a.max_steps >= 2u) {
+      double su = 0.0, sl = 0.0;
+      for (int w = 0; w < nw; ++w) {
+        su += red[1][w];
+        sl += red[2][w];
+      }
+      out_up[1] = su;
+      out_lo[1] = sl;
+    }
   }
-  __syncthreads();
-
-  // this thread's share of the convolution: output cells jb..jb+7 from the
-  // source cells [i0, i1) of its group
-  // Split boundaries after the first sit at sources i = M - 1 (mod 8): there
-  // the incoming row entries of every output block start an aligned group,
-  // so only the first split has a lead of single sources (and only the last
-  // a tail of one).
-  auto split_start = [&](uint32_t g) -> uint32_t {
-    if (g == 0u) return 0u;
-    if (g >= Q) return M;
-    const uint32_t base = (g * M) / Q, r = (M - 1u) & 7u;
-    return base < r ? 0u : base - ((base - r) & 7u);
-  };
-  const uint32_t jb = blk * kOut, i0 = split_start(q), i1 = split_start(q + 1u);
-  const bool active = blk < nb;
+  // Block-diagonals holding an entry of the band (diagonal d covers
+  // displacements 16 d - 15 .. 16 d + 15) whose mass blocks a - d, for the
+  // columns a of this wavefront's tile, reach the grid: a contiguous range,
+  // split into G contiguous shares, one per group.  All wave-uniform.
+  // (the lowest d with 16 d + 15 >= band[0], the highest with 16 d - 15 <= band[1])
+  const int dlo = ceil_div16(band[0] - 15), dhi = floor_div16(band[1] + 15);
+  const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)wave);
+  const uint32_t tile = wv / G, grp = wv - tile * G;
+  const int nbi = (int)NB, c0 = 16 * (int)tile;
+  const int dA = max(dlo, c0 - nbi + 1), dB = min(dhi, min(c0 + 15, nbi - 1));
+  const int nd = dB >= dA ? dB - dA + 1 : 0;
+  const int dS = dA + (nd * (int)grp) / (int)G, dE = dA + (nd * ((int)grp + 1)) / (int)G;
+  const int l16 = lane & 15, l4 = lane >> 4;
   double* cur = m0;
   double* nxt = m1;
   uint32_t n = 2;
   for (; n <= a.max_steps; ++n) {
-    // absorbed at step n
-    double pu = 0.0, pl = 0.0;
-    for (uint32_t i = tid; i < M; i += nt) {
-      pu = fma(cur[i], upc[i], pu);
-      pl = fma(cur[i], loc[i], pl);
-    }
-    pu = wave_sum(pu);
-    pl = wave_sum(pl);
-    if (lane == 0) {
-      red[0][wave] = pu;
-      red[1][wave] = pl;
-    }
-    // survivor mass: a 1-D convolution with the kernel row.  The 8 row
-    // entries a thread needs for source cell i slide by one per i, so each
-    // LDS read of the row feeds 8 multiply-adds; the source mass cur[i] is
-    // the same for the whole wavefront (a broadcast read).
-    double acc[kOut];
+    // (A) this wavefront's share of T m on the matrix cores; the fragments
+    // of the next diagonal are read while the current products run
+    f64x4 C = {0.0, 0.0, 0.0, 0.0};
+    if (tile < NT) {
+      const double* fa = f + (int)geo.FOFF + l16 - l4;
+      const double* mb = cur + (c0 + l16 + nbi) * kBS + l4;
+      double A[4], B[4];
+      if (dS < dE) {
 #pragma unroll
-    for (int k = 0; k < kOut; ++k) acc[k] = 0.0;
-    if (active) {
-      const int x0 = (int)jb - (int)i0 + (int)(M - 1);  // row entry of (jb, i0)
-      double w[kOut];
+        for (int q = 0; q < 4; ++q) {
+          A[q] = fa[16 * dS - 4 * q];
+          B[q] = mb[4 * q - dS * kBS];
+        }
+      }
+      for (int d = dS; d < dE; ++d) {
+        double An[4], Bn[4];
+        const int dn = d + 1 < dE ? d + 1 : d;  // the last diagonal re-reads its own
 #pragma unroll
-      for (int k = 0; k < kOut; ++k) w[k] = f[fpos(x0 + k)];
-      // Source i brings in entry x0 - 1 - (i - i0) (>= -1: a zero pad entry
-      // at the end).  Sources whose incoming entries fill an aligned group
-      // 8m+7 .. 8m are taken 8 at a time: the group is read at once and the
-      // window slides by register renaming.  u0 mod 8 is the same for every
-      // thread of the split group, so the lead and tail lengths are uniform.
-      const uint32_t u0 = (uint32_t)(x0 - 1 + kFPad);
-      const uint32_t lead = min((((u0 & 7u) + 1u) & 7u), i1 - i0);
-      auto one = [&](uint32_t i) {
-        const double c = cur[i];
-#pragma unroll
-        for (int k = 0; k < kOut; ++k) acc[k] = fma(c, w[k], acc[k]);
-#pragma unroll
-        for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
-        w[0] = f[fpos(x0 - (int)(i - i0) - 1)];
-      };
-      uint32_t i = i0;
-      for (; i < i0 + lead; ++i) one(i);
-      auto group = [&](uint32_t i) {
-        const uint32_t ub = u0 - (i - i0);  // 8m + 7
-        const double* g = f + fpos_u(ub - 7u);
-        double nf[8], c8[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          nf[r] = g[r];
-          c8[r] = cur[i + r];
+        for (int q = 0; q < 4; ++q) {
+          An[q] = fa[16 * dn - 4 * q];
+          Bn[q] = mb[4 * q - dn * kBS];
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int q = 0; q < 4; ++q) C = __builtin_amdgcn_mfma_f64_16x16x4f64(A[q], B[q], C, 0, 0, 0);
 #pragma unroll
-          for (int k = 0; k < kOut; ++k) acc[k] = fma(c8[t], w[k], acc[k]);
-#pragma unroll
-          for (int k = kOut - 1; k > 0; --k) w[k] = w[k - 1];
-          w[0] = nf[7 - t];
+        for (int q = 0; q < 4; ++q) {
+          A[q] = An[q];
+          B[q] = Bn[q];
         }
-      };
-      // two groups per iteration: the window then returns to its registers
-      // every 16 sources rather than every 8 (fewer register moves)
-      for (; i + 16u <= i1; i += 16u) {
-        group(i);
-        group(i + 8u);
       }
-      if (i + 8u <= i1) {
-        group(i);
-        i += 8u;
-      }
-      for (; i < i1; ++i) one(i);
-      double* pq = part + q * PM;
+      double* pw = part + ((grp * NT + tile) * 4u) * 64u + (uint32_t)lane;
 #pragma unroll
-      for (int k = 0; k < kOut; ++k)
-        if (jb + k < M) pq[fpos_u(jb + k)] = acc[k];
+      for (int r = 0; r < 4; ++r) pw[r * 64] = C[r];
     }
     __syncthreads();
-    if (tid == 0) {
-      double su = 0.0, sl = 0.0;
-      for (int w = 0; w < nw; ++w) {
-        su += red[0][w];
-        sl += red[1][w];
-      }
-      out_up[n - 1] = su;
-      out_lo[n - 1] = sl;
-    }
-    // new mass of every cell: the splits' partial sums in split order, one
-    // cell per thread; and the survivor mass, to stop once it is negligible
+    // (B) the new mass: the groups' partial sums in group order; its total
+    // and the mass it will lose at either bound in the next step
     double sv = 0.0;
-    for (uint32_t j = tid; j < M; j += nt) {
-      const uint32_t pj = fpos_u(j);
-      double v = part[pj];
-      for (uint32_t r = 1; r < Q; ++r) v += part[r * PM + pj];
-      nxt[j] = v;
-      sv += v;
+    pu = 0.0;
+    pl = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const uint32_t t = tid + (uint32_t)k * nt;
+      if (t < 256u * NT) {
+        const double* pr = part + t;  // [grp][tile][r][l] with (tile, r, l) = t
+        double v = pr[0];
+        for (uint32_t g = 1; g < G; ++g) v += pr[g * NT * 256u];
+        if (!real[k]) v = 0.0;
+        nxt[pos[k]] = v;
+        sv += v;
+        pu = fma(v, upc[k], pu);
+        pl = fma(v, loc[k], pl);
+      }
     }
-    sv = wave_sum(sv);
-    if (lane == 0) red_sv[wave] = sv;
-    // One barrier per step besides the one after the partial sums: the next
-    // step's reads of the new mass and writes of partial sums and of red
-    // come after it, and every read of this step's partial sums and red
-    // comes before it.
+    // 16-lane row sums into the window's ring; whole sums once a window is
+    // full (the stop test and the absorbed masses need no per-step barrier
+    // of their own)
+    const uint32_t rows = nt >> 4, k = (n - 2u) % kWin;
+    sv = row_sum(sv);
+    pu = row_sum(pu);
+    pl = row_sum(pl);
+    if ((lane & 15) == 0) {
+      double* rw = ring + (k * 3u) * rows + (tid >> 4);
+      rw[0] = sv;
+      rw[rows] = pu;
+      rw[2u * rows] = pl;
+    }
+    // Reads of this step's partial sums and writes of the new mass come
+    // before this barrier; the next step's products read the new mass and
+    // overwrite the partial sums after it.
     __syncthreads();
-    double tot = 0.0;
-    for (int w = 0; w < nw; ++w) tot += red_sv[w];
     double* t = cur;
     cur = nxt;
     nxt = t;
-    if (tot < a.tol) break;
+    if (k == kWin - 1u || n == a.max_steps) {
+      // window steps n0 .. n: whole sums in row order, one per thread
+      const uint32_t cnt = k + 1u, n0 = n - k;
+      if (tid < 3u * cnt) {
+        const uint32_t q = tid / cnt, kk = tid - q * cnt;
+        const double* rw = ring + (kk * 3u + q) * rows;
+        double v = 0.0;
+        for (uint32_t r = 0; r < rows; ++r) v += rw[r];
+        wsum[q][kk] = v;
+      }
+      __syncthreads();
+      // the first step of the window whose survivor mass is below tol
+      uint32_t stop = cnt;
+      for (uint32_t kk = 0; kk < cnt; ++kk)
+        if (wsum[0][kk] < a.tol) {
+          stop = kk;
+          break;
+        }
+      // absorbed at step m + 1, for the window's steps m before the stop
+      if (tid < stop) {
+        const uint32_t m = n0 + tid;
+        if (m < a.max_steps) {
+          out_up[m] = wsum[1][tid];
+          out_lo[m] = wsum[2][tid];
+        }
+      }
+      if (stop < cnt) {
+        n = n0 + stop;
+        break;
+      }
+    }
   }
-  for (uint32_t k = n + 1 + tid; k <= a.max_steps; k += nt) {
-    out_up[k - 1] = 0.0;
-    out_lo[k - 1] = 0.0;
+  if (n > a.max_steps) n = a.max_steps + 1u;
+  // after a stop at step n, steps n + 1 .. N absorb nothing
+  for (uint32_t k = n + tid; k < a.max_steps; k += nt) {
+    out_up[k] = 0.0;
+    out_lo[k] = 0.0;
   }
 }
 
 }  // namespace
 
-// LDS: the kernel row (frow_slots), two mass vectors, the partial sums of
-// the splits and the two absorption tables.
-size_t density_lds_bytes(uint32_t cells, uint32_t splits) {
-  return ((size_t)frow_slots(cells) + 4u * (size_t)cells + (size_t)splits * prow_slots(cells)) * sizeof(double);
-}
-
-uint32_t density_threads_per_split(uint32_t cells) {
-  const uint32_t nb = (cells + kOut - 1) / kOut;
-  return ((nb + 63) / 64) * 64;
+// LDS: the kernel row, two zero-padded mass vectors, the partial sums and
+// the window's row sums.
+size_t density_lds_bytes(uint32_t cells) {
+  const DensityGeo g = density_geo(cells);
+  return ((size_t)g.FW + 2u * (size_t)g.CB * kBS + (size_t)g.G * g.NT * 256u +
+          (size_t)kWin * 3u * (g.W * 64u / 16u)) * sizeof(double);
 }
 
 hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st) {
-  const uint32_t tpq = density_threads_per_split(a.cells);
-  if (a.splits < 1 || a.splits * tpq > (uint32_t)kMaxThreads) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ddm_density_kernel, dim3((uint32_t)a.n_settings), dim3(a.splits * tpq),
-                     density_lds_bytes(a.cells, a.splits), st, a);
+  const DensityGeo g = density_geo(a.cells);
+  if (a.cells < 16u || g.W * 64u > (uint32_t)kMaxThreads || 2u * g.W * 64u < 256u * g.NT)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ddm_density_kernel, dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
+                     density_lds_bytes(a.cells), st, a);
   return hipGetLastError();
 }
 

@@ -180,7 +180,6 @@ struct LoopArgs {
 struct DensityArgs {
   uint64_t n_settings;
   uint32_t max_steps, cells, n_signals;
-  uint32_t splits;  // thread groups splitting each step's source cells (1..8)
   double dt, drift, b, thresh, start, tol;
   const double* grid;
   double* out;  // [settings][2][max_steps]
@@ -207,7 +206,6 @@ hipError_t launch_uf_step(const UnfusedArgs& a, int precision, uint32_t n, int c
                           hipStream_t st);
 hipError_t launch_uf_reduce(const UnfusedArgs& a, hipStream_t st);
 hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st);
-size_t density_lds_bytes(uint32_t cells, uint32_t splits);
-uint32_t density_threads_per_split(uint32_t cells);
+size_t density_lds_bytes(uint32_t cells);
 
 }  // namespace cm
