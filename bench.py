@@ -175,7 +175,7 @@ def parse():
                     help="skip the CPU oracle leg (used under the profiler)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (no rate network, no served mix)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served-mix arrival window")
     ap.add_argument("--workload", choices=sorted(SIDE_WORKLOADS), default=None,
                     help="time one other workload of the path instead (prints its own JSON "
@@ -254,6 +254,7 @@ def serving(cm, seconds):
     t0 = min(r.arrival for r in done)
     t1 = max(r.done for r in done)
     summ = serve.latency_summary(done)
+    summ["by_config"] = serve.latency_by_config(done)
     summ.update({"arrival_rate_hz": 50.0, "window_s": float(mix[-1][0]),
                  "agg_run_steps_per_s": steps / (t1 - t0), "run_steps": int(steps),
                  "budget_gib": 32, "streams": 4,

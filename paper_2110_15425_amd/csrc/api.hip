@@ -649,7 +649,13 @@ cm_status launch_loop_sweep(cm_handle* h, const cm_model* m, const cm_sweep* s, 
   const uint32_t team = cm::loop_team_lanes(a.J, a.total_runs, (uint32_t)h->cu_count);
   const uint64_t teams_per_block = 256u / team;
   const uint64_t want = (a.total_runs + teams_per_block - 1) / teams_per_block;
-  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * h->cu_count));
+  // Teams take runs in a fixed stride, so a workgroup's work varies with its
+  // runs' lengths; with several rounds of workgroups the dispatcher refills
+  // freed slots and evens that out (measured on MI355X: wavefront teams 10 %
+  // faster at 32 workgroups per CU than at 8, one run per team slower;
+  // workgroup teams best at 8)
+  const uint64_t per_cu = team == 256u ? 8u : 32u;
+  const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, per_cu * h->cu_count));
   hipError_t e;
   ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");

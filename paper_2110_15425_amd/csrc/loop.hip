@@ -17,13 +17,18 @@
 // allocations, over too few runs to fill the GPU with wavefront teams, takes
 // the whole workgroup (P = 256).  Lane i of the team evaluates allocations
 // i, i + P, ... with all their samples (four at a time when it has several,
-// so that independent random-number chains overlap); a butterfly of
-// cross-lane moves (DPP within 16-lane rows, shuffles across them), and for P = 256 a fold of the four wavefronts' results through
-// LDS, then finds the best (score, priority, allocation) and the second-best
-// score, leaving the same result in every lane.  Every lane of the team then
-// applies the chosen step to its own copy of the state (identical
-// arithmetic, identical bits), so the team never broadcasts and its control
-// flow stays uniform.  Teams take runs in a fixed stride, and a finished run
+// so that independent random-number chains overlap).  A wavefront team finds
+// the best score by one minimum over the wavefront, the winner by a ballot of
+// the lanes at it (exact ties, rare, by the smallest (priority, allocation)),
+// and the second-best score by a second minimum; smaller teams use a
+// butterfly of (score, second score, allocation) cross-lane moves (DPP within
+// 16-lane rows, shuffles across them), and P = 256 adds a fold of the four
+// wavefronts' results through LDS.  Every lane of the team then applies the
+// chosen step to its own copy of the state (identical arithmetic, identical
+// bits), so the team never broadcasts and its control flow stays uniform; a
+// wavefront team draws the normals of its run's own steps 64 at a time, one
+// step per lane, and reads each step's from its lane.  Teams take runs in a
+// fixed stride, and a finished run
 // is counted straight into global memory by the team's first lane: a run
 // costs L^2 M look-ahead steps per step, so the atomics are negligible.  The
 // allocation drive table [L^2][9][2] and the allocations' squared norms
@@ -43,28 +48,39 @@ constexpr uint32_t kStreamLook = 0x80000000u;  // | (allocation * M + sample)
 constexpr uint32_t kStreamPick = 0xC0000000u;  // | allocation
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// One LCA step in the model's precision: the arithmetic of the open-loop
-// LCA kernel, so that a one-allocation loop reproduces it bit for bit.
+// One LCA step in the model's precision from its normals (z0, z1 in FP64;
+// zf0, zf1 in FP32 steps, with idt_i = float(I_i dt)): the arithmetic of the
+// open-loop LCA kernel, so that a one-allocation loop reproduces it bit for
+// bit.
 template <int PREC>
-__device__ __forceinline__ void lca_step(const LoopArgs& a, double x0, double x1, double in0,
-                                         double in1, const Words& w, double& y0, double& y1) {
+__device__ __forceinline__ void lca_update(const LoopArgs& a, double x0, double x1, double in0,
+                                           double in1, float idt0, float idt1, double z0, double z1,
+                                           float zf0, float zf1, double& y0, double& y1) {
   if (PREC == CM_FP64) {
-    double z0, z1;
-    normals64(w, z0, z1);
     y0 = (x0 + (((in0 - a.leak * x0) - a.comp * x1) * a.dt)) + a.b * z0;
     y1 = (x1 + (((in1 - a.leak * x1) - a.comp * x0) * a.dt)) + a.b * z1;
   } else {
-    float z0, z1;
-    normals32(w, z0, z1);
     const LcaF32 pf = lca_f32(a.leak, a.comp, a.dt, a.b);
     const float xf0 = (float)x0, xf1 = (float)x1;
-    y0 = x0 + (double)lca_inc_f32(pf, (float)(in0 * a.dt), xf0, xf1, z0);
-    y1 = x1 + (double)lca_inc_f32(pf, (float)(in1 * a.dt), xf1, xf0, z1);
+    y0 = x0 + (double)lca_inc_f32(pf, idt0, xf0, xf1, zf0);
+    y1 = x1 + (double)lca_inc_f32(pf, idt1, xf1, xf0, zf1);
   }
   if (a.nonneg) {
     if (y0 < 0.0) y0 = 0.0;
     if (y1 < 0.0) y1 = 0.0;
   }
+}
+
+// The same step from a random block.
+template <int PREC>
+__device__ __forceinline__ void lca_step(const LoopArgs& a, double x0, double x1, double in0,
+                                         double in1, float idt0, float idt1, const Words& w,
+                                         double& y0, double& y1) {
+  double z0 = 0.0, z1 = 0.0;
+  float zf0 = 0.0f, zf1 = 0.0f;
+  if (PREC == CM_FP64) normals64(w, z0, z1);
+  else normals32(w, zf0, zf1);
+  lca_update<PREC>(a, x0, x1, in0, in1, idt0, idt1, z0, z1, zf0, zf1, y0, y1);
 }
 
 // Tie rule among allocations with equal scores: the smaller (Philox priority,
@@ -101,6 +117,40 @@ __device__ __forceinline__ double partner(double v) {
   return __longlong_as_double((long long)(lo | (hi << 32)));
 }
 
+// Lane src's value (src wave-uniform).
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __longlong_as_double((long long)((uint64_t)lo | ((uint64_t)hi << 32)));
+}
+
+// Minimum over the wavefront, the same value in every lane (all lanes
+// active; NaN loses to any number, as the scan's comparisons ignore it).
+__device__ __forceinline__ double wave_min(double v) {
+  v = fmin(v, partner<0>(v));
+  v = fmin(v, partner<1>(v));
+  v = fmin(v, partner<2>(v));
+  v = fmin(v, partner<3>(v));
+  v = fmin(v, partner<4>(v));
+  v = fmin(v, partner<5>(v));
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  auto step = [&](auto round) {
+    constexpr int R = decltype(round)::value;
+    const uint64_t o = (uint64_t)partner<R>((uint32_t)v) | ((uint64_t)partner<R>((uint32_t)(v >> 32)) << 32);
+    v = o < v ? o : v;
+  };
+  step(std::integral_constant<int, 0>{});
+  step(std::integral_constant<int, 1>{});
+  step(std::integral_constant<int, 2>{});
+  step(std::integral_constant<int, 3>{});
+  step(std::integral_constant<int, 4>{});
+  step(std::integral_constant<int, 5>{});
+  return v;
+}
+
 template <int PREC, int P, int U>
 __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
   // P = kLoopBlock: the whole workgroup is one team; its four wavefronts
@@ -118,7 +168,10 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
   const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
   const uint32_t T = (uint32_t)a.trials, J = a.J, M = a.M, N = a.max_steps;
   const double th = a.thresh, eps = a.flag_eps;
-  for (uint64_t run = (uint64_t)blockIdx.x * teams_per_block + threadIdx.x / P; run < a.total_runs;
+  // a wavefront-or-wider team's run index is the same in every lane
+  const uint32_t team = P >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / P) : threadIdx.x / P;
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint64_t run = (uint64_t)blockIdx.x * teams_per_block + team; run < a.total_runs;
        run += n_teams) {
     const uint32_t s = (uint32_t)(run / T), t = (uint32_t)(run - (uint64_t)s * T);
     const uint32_t stim = t % 9u;
@@ -131,9 +184,21 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
     double x0 = 0.0, x1 = 0.0;
     bool flag = false;
     int choice = -1;
+    // P = 64: the run's own normals for steps 64 b .. 64 b + 63, lane i
+    // holding step 64 b + i's (drawn when step 64 b comes up, read back by
+    // lane each step: one block per wavefront and 64 steps)
+    double ez0 = 0.0, ez1 = 0.0;
+    float ef0 = 0.0f, ef1 = 0.0f;
     uint32_t n = 1;
     for (; n <= N; ++n) {
       const uint32_t k = n - 1u;
+      if constexpr (P == 64) {
+        if ((k & 63u) == 0u) {
+          const Words w = philox(k + lane, t, s, 0u, k0, k1);
+          if (PREC == CM_FP64) normals64(w, ez0, ez1);
+          else normals32(w, ef0, ef1);
+        }
+      }
       const double dx = c ? x1 - x0 : x0 - x1;  // x_c - x_w
       double bv = INFINITY, sv = INFINITY;
       uint32_t bj = kNone;
@@ -144,6 +209,7 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
       // allocation j and are discarded.
       for (uint32_t j = j0; j < J; j += U * P) {
         double gs[U], i0[U], i1[U];
+        float f0[U], f1[U];
         uint32_t ju[U];
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
@@ -151,6 +217,10 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           const double* d = a.drive + ((uint64_t)ju[u] * 9u + stim) * 2u;
           i0[u] = d[0];
           i1[u] = d[1];
+          if constexpr (P == 64) {  // rounded once per allocation and step
+            f0[u] = (float)(i0[u] * a.dt);
+            f1[u] = (float)(i1[u] * a.dt);
+          }
           gs[u] = 0.0;
         }
         for (uint32_t m = 0; m < M; ++m) {
@@ -158,7 +228,11 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           for (uint32_t u = 0; u < U; ++u) {
             const Words w = philox(k, t, s, kStreamLook | (ju[u] * M + m), k0, k1);
             double y0, y1;
-            lca_step<PREC>(a, x0, x1, i0[u], i1[u], w, y0, y1);
+            if constexpr (P == 64)
+              lca_step<PREC>(a, x0, x1, i0[u], i1[u], f0[u], f1[u], w, y0, y1);
+            else
+              lca_step<PREC>(a, x0, x1, i0[u], i1[u], (float)(i0[u] * a.dt), (float)(i1[u] * a.dt), w,
+                             y0, y1);
             gs[u] = gs[u] + ((c ? y1 - y0 : y0 - y1) - dx);
           }
         }
@@ -180,9 +254,34 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           }
         }
       }
+      bool near_pick = false;
+      if constexpr (P == 64) {
+        // The best score over the wavefront; an exact tie anywhere (several
+        // lanes at it, or a lane holding two allocations at it) goes to the
+        // smallest (priority, allocation), else the one lane at it holds the
+        // winner.  The second-lowest score is the winner's own second or
+        // another lane's best; exact ties leave none above the best.
+        const double gb = wave_min(bv);
+        const bool at = bv == gb;
+        const uint64_t tied = __builtin_amdgcn_ballot_w64(at);
+        const bool tie = __popcll(tied) > 1 || __builtin_amdgcn_ballot_w64(sv == gb) != 0;
+        uint32_t pick;
+        if (__builtin_expect(!tie, 1)) {
+          pick = (uint32_t)__builtin_amdgcn_readlane((int)bj, (int)__builtin_ctzll(tied));
+        } else {
+          uint64_t key = ~0ull;
+          if (at && bj != kNone)
+            key = ((uint64_t)philox(k, t, s, kStreamPick | bj, k0, k1).w0 << 32) | bj;
+          pick = (uint32_t)wave_min_u64(key);
+        }
+        const double second = wave_min(at ? sv : bv);
+        near_pick = !tie && second > gb && second - gb < eps;
+        bv = gb;
+        bj = pick;
+      }
       auto join = [&](auto round) {
         constexpr int R = decltype(round)::value;
-        if constexpr ((1 << R) < (P < 64 ? P : 64)) {
+        if constexpr (P != 64 && (1 << R) < (P < 64 ? P : 64)) {
           const double ov = partner<R>(bv), os = partner<R>(sv);
           const uint32_t oj = partner<R>(bj);
           const double ns = fmin(fmin(sv, os), fmax(bv, ov));
@@ -222,12 +321,28 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
           sv = ns;
         }
       }
-      if (sv > bv && sv - bv < eps) flag = true;
+      if (P == 64 ? near_pick : (sv > bv && sv - bv < eps)) flag = true;
       // the step itself, with the chosen allocation, on the run's own stream
       // (allocation 0 if no score compared as a number)
       const double* d = a.drive + ((uint64_t)(bj == kNone ? 0u : bj) * 9u + stim) * 2u;
+      const double e0 = d[0], e1 = d[1];
+      const float g0 = (float)(e0 * a.dt), g1 = (float)(e1 * a.dt);
       double y0, y1;
-      lca_step<PREC>(a, x0, x1, d[0], d[1], philox(k, t, s, 0u, k0, k1), y0, y1);
+      if constexpr (P == 64) {
+        const int src = (int)(k & 63u);
+        double z0 = 0.0, z1 = 0.0;
+        float zf0 = 0.0f, zf1 = 0.0f;
+        if (PREC == CM_FP64) {
+          z0 = read_lane(ez0, src);
+          z1 = read_lane(ez1, src);
+        } else {
+          zf0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef0), src));
+          zf1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef1), src));
+        }
+        lca_update<PREC>(a, x0, x1, e0, e1, g0, g1, z0, z1, zf0, zf1, y0, y1);
+      } else {
+        lca_step<PREC>(a, x0, x1, e0, e1, g0, g1, philox(k, t, s, 0u, k0, k1), y0, y1);
+      }
       x0 = y0;
       x1 = y1;
       if (fabs(x0 - th) < eps || fabs(x1 - th) < eps) flag = true;

@@ -206,7 +206,31 @@ def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4, dumps=False):
     return sch.finished
 
 
+CONFIG_NAMES = {0: "ddm", 1: "conflict", 2: "grid_search", 3: "rate_network"}
+
+
+def config_of(w):
+    """Which of the mix's four model configurations a request is (0 DDM,
+    1 conflict network, 2 its scored grid search, 3 rate network)."""
+    kind = int(w["kind"])
+    if kind == W.DDM:
+        return 0
+    if kind == W.RNN:
+        return 3
+    return 2 if float(w.get("reward", 0.0)) != 0.0 or float(w.get("cost", 0.0)) != 0.0 else 1
+
+
 def latency_summary(finished):
     lat = np.array([r.done - r.arrival for r in finished]) * 1e3
     return dict(requests=len(lat), p50_ms=float(np.percentile(lat, 50)),
                 p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()))
+
+
+def latency_by_config(finished):
+    """latency_summary per model configuration, keyed by its name."""
+    out = {}
+    for c, name in CONFIG_NAMES.items():
+        sel = [r for r in finished if config_of(r.w) == c]
+        if sel:
+            out[name] = latency_summary(sel)
+    return out

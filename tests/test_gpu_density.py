@@ -69,3 +69,21 @@ def test_density_64_drifts_full_size_sampled():
     # the drift orders the settings: more drift, more mass on the upper bound
     upper = out[:, 1].sum(axis=1)
     assert np.all(np.diff(upper) > 0)
+
+
+def test_density_256_drifts_full_size_sampled():
+    """The 256-setting sweep that fills every compute unit (one workgroup per
+    setting), 1000 cells, 3000 steps, as timed: four settings against the
+    oracle, and the first-passage mass of every setting sums to one minus its
+    survivor mass below tol."""
+    drifts = [0.3 * (i + 1) / 256 for i in range(256)]
+    w = W.ddm(drifts=drifts)
+    out = cm.ddm_density(w, cells=1000, tol=1e-15)
+    assert out.shape == (256, 2, 3000)
+    for s in (0, 100, 201, 255):
+        lo, up = oracle.ddm_density(drifts[s] * 0.01, math.sqrt(0.01), 1.0, cells=1000,
+                                    max_steps=3000, tol=1e-15)
+        np.testing.assert_allclose(out[s, 0], lo, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(out[s, 1], up, rtol=0, atol=1e-12)
+    total = out.sum(axis=(1, 2))
+    assert np.all(np.abs(total - 1.0) < 1e-9)

@@ -96,3 +96,22 @@ def test_served_mix_recipe():
         assert 1 <= w["n_settings"] <= 4096
         assert runs >= 1 and w["trials"] >= 1
         assert w["seed"] >= 1000
+
+
+def test_latency_by_config_groups_requests_by_model_configuration():
+    """Each served request belongs to exactly one of the four configurations,
+    and the per-configuration summaries cover every finished request."""
+    mix = serve.served_mix(200, rate_hz=50.0, seed=11)
+    names = [serve.CONFIG_NAMES[serve.config_of(w)] for _, w in mix]
+    assert set(names) == set(serve.CONFIG_NAMES.values())
+
+    class Done:
+        def __init__(self, w, lat):
+            self.w, self.arrival, self.done = w, 0.0, lat
+
+    finished = [Done(w, 0.001 * (1 + i % 7)) for i, (_, w) in enumerate(mix)]
+    by = serve.latency_by_config(finished)
+    assert sum(v["requests"] for v in by.values()) == len(finished)
+    for name, v in by.items():
+        assert v["requests"] == names.count(name)
+        assert 1.0 <= v["p50_ms"] <= v["p99_ms"] <= v["max_ms"] <= 7.0
