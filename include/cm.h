@@ -188,10 +188,17 @@ typedef struct {
  *                 of the launch has at most 2^20 runs, else 1).  The
  *                 wavefront form runs 8 wavefronts per workgroup when the
  *                 launch has at most 2^17 runs, else 4 (the block knob
- *                 does not apply to it).  Results do not depend on these
- *                 choices. */
+ *                 does not apply to it).
+ *  waves_per_simd DDM and conflict LCA, one lane per run: 0 (the compiler's
+ *                 register allocation), or 4 or 8: the kernel built with its
+ *                 registers capped so that 4 or 8 wavefronts fit on each
+ *                 SIMD -- the register use versus occupancy study of the
+ *                 paper's GPU kernels (Sec. 6.3); a cap below the kernel's
+ *                 own use spills or recomputes values.  Other values:
+ *                 CM_E_UNSUPPORTED.  The time-course variant ignores it.
+ * Results do not depend on these choices. */
 typedef struct {
-  uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run;
+  uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run, waves_per_simd;
 } cm_tuning;
 
 /* Pure host checks of a model/sweep pair (the rules above and the kind's

@@ -3,8 +3,12 @@
 For a given workload it times the simulation kernel (HIP events that libcm
 records around it) for each candidate launch shape and keeps the fastest.
 The knobs are the ones in ``cm_tuning``: runs handed to a workgroup per lane
-(which trades occupancy against the tail of long runs) and steps between
-refills of finished lanes (which trades idle lanes against refill cost).
+(which trades occupancy against the tail of long runs), steps between
+refills of finished lanes (which trades idle lanes against refill cost) and,
+for the lane kernels, the register cap that sets how many wavefronts fit per
+SIMD (the register use versus occupancy trade-off of the paper's GPU
+kernels: more wavefronts hide more latency, but a cap below the kernel's own
+register use spills).
 Results can be persisted in a JSON cache keyed by device, kind, precision
 and a size class of the sweep, so a later process reuses them without
 re-timing.
@@ -21,6 +25,7 @@ from . import cm
 RUNS_PER_LANE = (1, 2, 4, 6, 8, 12, 16, 32)
 STEPS_PER_SYNC = (2, 4, 8, 12, 16, 32)
 RUNS_PER_WAVE = (1, 2, 4, 8, 16, 32, 64)  # DDM, one wavefront per run
+WAVES_PER_SIMD = (0, 4, 8)  # 0: the compiler's register allocation
 
 
 def size_class(w):
@@ -66,7 +71,8 @@ def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=
     """Time every candidate shape on workload ``w`` (a workload dict, or a list
     of workloads of one kind and precision timed as one batched launch);
     install and return the best as (tuning dict, kernel ms, table of
-    (rpl, sps, lpr, ms)).  Shapes within a few per cent of each other are
+    (rpl, sps, lpr, ms), then (rpl, sps, lpr, ms, waves cap) for the
+    occupancy variants of the best shape).  Shapes within a few per cent of each other are
     not told apart by one timing, so the ``finalists`` fastest are timed
     ``rounds`` more times and ranked by their fastest timing."""
     ws = w if isinstance(w, list) else [w]
@@ -91,7 +97,23 @@ def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=
             ms = min(ms, time_shape(handle, ds, reps))
         table[i] = (rpl, sps, lpr, ms)
     rpl, sps, lpr, ms = min(table, key=lambda r: r[3])
-    handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr)
+    # the occupancy axis, on the best shape: registers capped for 4 or 8
+    # wavefronts per SIMD against the compiler's own allocation
+    waves = 0
+    if kind in (0, 1) and lpr != 64:
+        best = ms
+        for wv in WAVES_PER_SIMD[1:]:
+            handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps,
+                              lanes_per_run=lpr, waves_per_simd=wv)
+            t = min(time_shape(handle, ds, reps) for _ in range(rounds))
+            table.append((rpl, sps, lpr, t, wv))
+            if verbose:
+                print(f"  waves/SIMD cap {wv}: {t:.4f} ms", flush=True)
+            if t < best:
+                best, waves = t, wv
+        ms = best
+    handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr,
+                      waves_per_simd=waves)
     return handle.get_tuning(kind, prec), ms, table
 
 

@@ -712,7 +712,8 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   if ((e = cm::launch_prep(pb, stream)) != hipSuccess) return hip_fail(e, "sweep preparation");
   ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
-  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan_block, tc.every != 0, b, lds, stream)) != hipSuccess)
+  if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan_block, tc.every != 0,
+                               h->tune[kind][prec].waves_per_simd, b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_score(sb, stream)) != hipSuccess) return hip_fail(e, "score kernel");
@@ -906,6 +907,10 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
   if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
   if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");
   if (v.tile_rows != 16) return fail(CM_E_UNSUPPORTED, "tile_rows must be 16");
+  if (v.waves_per_simd != 0 && v.waves_per_simd != 4 && v.waves_per_simd != 8)
+    return fail(CM_E_UNSUPPORTED, "waves_per_simd must be 0, 4 or 8");
+  if (v.waves_per_simd && kind != CM_DDM && kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "waves_per_simd applies to the DDM and conflict-LCA lane kernels");
   h->tune[kind][precision] = v;
   return ok();
 }

@@ -188,8 +188,10 @@ struct DensityArgs {
 // Launchers (return the hipError_t of the launch).
 // scan_block: 0 for the lane kernel, else the DDM scan kernel with that many
 // threads (256 or 512) per workgroup.
-hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, const LaneBatch& b,
-                           size_t lds_bytes, hipStream_t st);
+// occ: 0, or 4 / 8 for the lane kernel built with registers capped so that
+// that many wavefronts fit per SIMD (ignored by the scan kernel).
+hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, uint32_t occ,
+                           const LaneBatch& b, size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
                           double* out, hipStream_t st);

@@ -536,8 +536,14 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
 // tc_every steps (one sweep per launch in practice; the LDS window then holds
 // each setting's time-course block after all the settings' records, and the
 // drain stage follows them).
-template <class M, bool TC>
-__global__ __launch_bounds__(kBlock) void sim_lane_kernel(LaneBatch batch) {
+//
+// OCC: 0 leaves register allocation to the compiler; 4 or 8 caps the
+// registers so that that many wavefronts fit on each SIMD (the register use
+// versus occupancy trade-off of the paper's GPU study, Sec. 6.3; a cap below
+// the kernel's natural use spills or recomputes values).
+template <class M, bool TC, int OCC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1)))
+void sim_lane_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
   uint32_t* lds = (uint32_t*)lds_u64;
   __shared__ uint32_t next;
@@ -793,19 +799,25 @@ __global__ __launch_bounds__(kBlock) void ceiling_kernel(SimArgs a, uint32_t ste
 }
 
 template <class M>
-hipError_t launch_model(const LaneBatch& b, bool tc, size_t lds, hipStream_t st) {
+hipError_t launch_model(const LaneBatch& b, bool tc, uint32_t occ, size_t lds, hipStream_t st) {
+  const dim3 grid(b.base[b.n]), block(kBlock);
   if (tc)
-    hipLaunchKernelGGL((sim_lane_kernel<M, true>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL((sim_lane_kernel<M, true, 0>), grid, block, lds, st, b);
+  else if (occ == 4)
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 4>), grid, block, lds, st, b);
+  else if (occ == 8)
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 8>), grid, block, lds, st, b);
   else
-    hipLaunchKernelGGL((sim_lane_kernel<M, false>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 0>), grid, block, lds, st, b);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, const LaneBatch& b,
-                           size_t lds_bytes, hipStream_t st) {
-  if (b.n < 1 || b.n > kMaxBatch || (scan_block && tc)) return hipErrorInvalidValue;
+hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, uint32_t occ,
+                           const LaneBatch& b, size_t lds_bytes, hipStream_t st) {
+  if (b.n < 1 || b.n > kMaxBatch || (scan_block && tc) || (occ && occ != 4 && occ != 8))
+    return hipErrorInvalidValue;
   if (scan_block) {
     if (kind != CM_DDM || (scan_block != 256u && scan_block != (uint32_t)kScanBlockMax))
       return hipErrorInvalidValue;
@@ -816,10 +828,10 @@ hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc
     return hipGetLastError();
   }
   if (kind == CM_DDM)
-    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, tc, lds_bytes, st)
-                                : launch_model<DDM<CM_FP32_STEP>>(b, tc, lds_bytes, st);
-  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, lds_bytes, st)
-                              : launch_model<LCA<CM_FP32_STEP>>(b, tc, lds_bytes, st);
+    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, tc, occ, lds_bytes, st)
+                                : launch_model<DDM<CM_FP32_STEP>>(b, tc, occ, lds_bytes, st);
+  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, occ, lds_bytes, st)
+                              : launch_model<LCA<CM_FP32_STEP>>(b, tc, occ, lds_bytes, st);
 }
 
 size_t lane_stage_bytes(int kind, int precision) {

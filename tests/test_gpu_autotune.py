@@ -18,11 +18,18 @@ def test_tune_installs_the_fastest_listed_shape():
     w = W.conflict(trials=400, precision=W.FP32_STEP)
     before = cm.run(w, handle=h)
     t, ms, table = autotune.tune(h, w, reps=2, candidates=CANDS, finalists=2, rounds=2)
-    assert len(table) == len(CANDS)
-    assert {(r[0], r[1]) for r in table} == set(CANDS)
-    best = min(table, key=lambda r: r[3])
+    shapes = [r for r in table if len(r) == 4]
+    caps = [r for r in table if len(r) == 5]
+    assert len(shapes) == len(CANDS)
+    assert {(r[0], r[1]) for r in shapes} == set(CANDS)
+    best = min(shapes, key=lambda r: r[3])
     assert (t["runs_per_lane"], t["steps_per_sync"]) == (best[0], best[1])
-    assert ms == best[3] > 0
+    # the occupancy axis: the register caps timed on the best shape
+    assert [r[4] for r in caps] == [4, 8]
+    assert all((r[0], r[1]) == (best[0], best[1]) for r in caps)
+    fastest = min([best[3]] + [r[3] for r in caps])
+    assert ms == fastest > 0
+    assert t["waves_per_simd"] in (0, 4, 8)
     assert h.get_tuning(W.LCA, W.FP32_STEP) == t
     after = cm.run(w, handle=h)
     for k in ("hist", "stats"):
@@ -64,3 +71,43 @@ def test_fixed_knobs_are_refused_not_ignored():
     h.set_tuning(W.RNN, W.BF16_PROJ, block=256, tile_rows=16)
     t = h.get_tuning(W.RNN, W.BF16_PROJ)
     assert (t["block"], t["tile_rows"]) == (256, 16)
+
+
+@pytest.mark.parametrize("kind", ["lca", "ddm"])
+def test_register_caps_leave_results_unchanged(kind):
+    """The FP64 lane kernels built with registers capped for 4 or 8
+    wavefronts per SIMD (the 8-wavefront build spills) compute exactly what
+    the default build computes, per run, and match the oracle."""
+    import oracle
+    from parity import assert_parity
+    h = cm.Handle(0)
+    if kind == "lca":
+        w = W.conflict(trials=700, grid=W.control_grid(6), reward=1.0, cost=0.1, seed=21)
+        k = W.LCA
+    else:
+        w = W.ddm(trials=4000, drifts=np.linspace(-0.3, 0.5, 5), seed=22)
+        k = W.DDM
+    outs = []
+    for wv in (0, 4, 8):
+        h.set_tuning(k, W.FP64, waves_per_simd=wv, lanes_per_run=1 if kind == "ddm" else 0)
+        assert h.get_tuning(k, W.FP64)["waves_per_simd"] == wv
+        outs.append(cm.run(w, dumps=True, handle=h))
+    for o in outs[1:]:
+        for key in ("hist", "stats", "run_choice", "run_step", "run_flag", "run_state"):
+            assert np.array_equal(outs[0][key], o[key]), key
+    orc = oracle.run(w, dumps=True)
+    correct = [1]
+    if kind == "lca":
+        correct = oracle.conflict_correct(w["weights"], w["params"][W.LCA_P["hid_gain"]],
+                                          w["params"][W.LCA_P["hid_bias"]])
+    assert_parity(w, outs[2], orc, correct)
+
+
+def test_register_cap_rejected_where_not_built():
+    h = cm.Handle(0)
+    with pytest.raises(cm.CmError) as e:
+        h.set_tuning(W.LCA, W.FP64, waves_per_simd=6)
+    assert e.value.status == cm.E_UNSUPPORTED
+    with pytest.raises(cm.CmError) as e:
+        h.set_tuning(W.RNN, W.BF16_PROJ, waves_per_simd=4)
+    assert e.value.status == cm.E_UNSUPPORTED
