@@ -397,8 +397,9 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
     rk = run_key(L.t, L.s, k0, k1);
   }
 
-  // One step from the block w; false once the run has ended (L.n is then its
-  // decision step n).  xf0, xf1: the float images of the state (FP32 steps).
+  // One step from the block w; false when the new state is near the
+  // threshold (L.n is then n).  xf0, xf1: the float images of the state
+  // (FP32 steps).
   template <class H>
   __device__ __forceinline__ bool one(const SimArgs& A, Lane& L, uint32_t n, const Words& w,
                                       float& xf0, float& xf1, const H& hook) {
@@ -424,31 +425,23 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
       L.n = n;
       hook(L, x0, x1);
     }
-    // cheap comparisons per step; the exact tests run only within 2 eps of
-    // the threshold, where a unit can be within flag distance or across.
-    // FP32 steps compare the float images of the new state (which the next
-    // step needs anyway) with the float image of the guard: rounding is
-    // monotone, so x >= guard implies float(x) >= float(guard).  The whole
-    // wavefront takes the branch when any lane is near (the exact tests
-    // are false for the others), so the test needs no per-lane mask.
-    const double th = A.thresh, eps = A.flag_eps;
+    // one cheap comparison per step: a lane whose new state is within 2 eps
+    // of the threshold (or across it) leaves the loop at this step, and the
+    // exact tests run once after the loop (advance).  FP32 steps compare the
+    // float images of the new state (which the next step needs anyway) with
+    // the float image of the guard: rounding is monotone, so x >= guard
+    // implies float(x) >= float(guard).
     bool near;
     if constexpr (PREC == CM_FP64) {
-      near = (x0 > x1 ? x0 : x1) >= th - 2.0 * eps;
+      near = (x0 > x1 ? x0 : x1) >= A.thresh - 2.0 * A.flag_eps;
     } else {
       xf0 = (float)x0;
       xf1 = (float)x1;
       near = (xf0 >= A.guard_f) | (xf1 >= A.guard_f);
     }
-    if (__builtin_expect(__builtin_amdgcn_ballot_w64(near) != 0, 0)) {
-      if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
-      const double mx = x0 > x1 ? x0 : x1;
-      if (mx >= th) {
-        L.choice = (x1 > x0) ? 1 : 0;
-        if (fabs(x0 - x1) < eps) L.flag = true;
-        L.n = n;
-        return false;
-      }
+    if (near) {
+      L.n = n;
+      return false;
     }
     return true;
   }
@@ -475,7 +468,18 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
                                           int steps, const H& hook) {
     // the step cap bounds the trip count, so the body needs no cap test
     const uint32_t t = uniform_trips((uint32_t)steps, A.max_steps - L.n);
-    if (!steps_loop(A, L, k0, k1, t, hook)) return false;
+    if (!steps_loop(A, L, k0, k1, t, hook)) {
+      // stopped near the threshold after step L.n: the exact tests
+      const double th = A.thresh, eps = A.flag_eps;
+      if (near_th(x0, th, eps) || near_th(x1, th, eps)) L.flag = true;
+      const double mx = x0 > x1 ? x0 : x1;
+      if (mx >= th) {
+        L.choice = (x1 > x0) ? 1 : 0;
+        if (fabs(x0 - x1) < eps) L.flag = true;
+        return false;
+      }
+      // within 2 eps below the threshold: the run goes on from step L.n
+    }
     if (L.n == A.max_steps) {  // the cap, reached without a crossing
       L.choice = -1;
       return false;
