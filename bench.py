@@ -65,10 +65,10 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "d7e0dc790115e2290390932e58267ad6aa4db73c685cac407c4fb6956e1b2b38",
+TRAFFIC = {"sources_sha256": "4bb05fcee0520618a8479d7e8448a0d57de623198c8cd944e2acb5b958a76618",
            "batch": 12,
-           # profiles/sim_lane_lca_fp32_conflict_batched.md
-           "bytes_per_launch": {6: 3315557, 8: 2826086}}
+           # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block"
+           "bytes_per_launch": {"4,512": 2837504}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
 
@@ -186,9 +186,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--shape", default=None, metavar="RPL,SPS",
-                    help="use this runs_per_lane,steps_per_sync for the batched launch instead "
-                         "of tuning it (so that separate profiler runs see the same shape)")
+    ap.add_argument("--shape", default=None, metavar="RPL,SPS[,BLOCK[,WAVES]]",
+                    help="use this runs_per_lane,steps_per_sync (and workgroup size, register "
+                         "cap) for the batched launch instead of tuning it (so that separate "
+                         "profiler runs see the same kernel)")
     return ap.parse_args()
 
 
@@ -357,8 +358,10 @@ def main():
     # untimed: choose the FP32 launch shape on this device
     wb = [W.with_(w32, seed=1 + i) for i in range(BATCH)]
     if args.shape:
-        rpl, sps = (int(v) for v in args.shape.split(","))
-        h_tuned.set_tuning(W.LCA, W.FP32_STEP, runs_per_lane=rpl, steps_per_sync=sps)
+        rpl, sps, *rest = (int(v) for v in args.shape.split(","))
+        h_tuned.set_tuning(W.LCA, W.FP32_STEP, runs_per_lane=rpl, steps_per_sync=sps,
+                           block=rest[0] if rest else 256,
+                           waves_per_simd=rest[1] if len(rest) > 1 else 0)
         tuned = h_tuned.get_tuning(W.LCA, W.FP32_STEP)
     else:
         tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
@@ -394,7 +397,7 @@ def main():
     kern_rate = head["run_steps"] / (head["kern_ms"] / 1e3)
     traffic = None
     if TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH:
-        traffic = TRAFFIC["bytes_per_launch"].get(tuned["runs_per_lane"])
+        traffic = TRAFFIC["bytes_per_launch"].get(f"{tuned['runs_per_lane']},{tuned['block']}")
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",
         "value": head["rate"],

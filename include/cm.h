@@ -172,8 +172,12 @@ typedef struct {
  * register-use versus occupancy trade-off the Distill paper measures on its
  * GPU kernels (Sec. 6.3) is what these choose between; cm_get_tuning
  * reports the stored values (runs_per_lane 0 = size-dependent).
- *  block          threads per workgroup of the lane kernels; only 256 is
- *                 supported (CM_E_UNSUPPORTED otherwise).
+ *  block          threads per workgroup of the lane kernels: 256, or 512 or
+ *                 1024 for the DDM and conflict-LCA lane kernels (a larger
+ *                 workgroup packs more unfinished runs together while its
+ *                 chunk drains; it takes block x runs_per_lane runs and
+ *                 stages block x ~64 bytes of LDS).  Other values, and other
+ *                 kinds: CM_E_UNSUPPORTED.  The time-course variant runs 256.
  *  runs_per_lane  lane-per-run kernels: runs handed to a workgroup per lane
  *                 (0: chosen per launch from the run count, 2..8).
  *  steps_per_sync lane-per-run kernels: steps between refills of finished

@@ -5,10 +5,11 @@ records around it) for each candidate launch shape and keeps the fastest.
 The knobs are the ones in ``cm_tuning``: runs handed to a workgroup per lane
 (which trades occupancy against the tail of long runs), steps between
 refills of finished lanes (which trades idle lanes against refill cost) and,
-for the lane kernels, the register cap that sets how many wavefronts fit per
-SIMD (the register use versus occupancy trade-off of the paper's GPU
-kernels: more wavefronts hide more latency, but a cap below the kernel's own
-register use spills).
+for the lane kernels, the workgroup size (how many unfinished runs one
+workgroup packs together while its chunk drains) and the register cap that
+sets how many wavefronts fit per SIMD (the register use versus occupancy
+trade-off of the paper's GPU kernels: more wavefronts hide more latency, but
+a cap below the kernel's own register use spills).
 Results can be persisted in a JSON cache keyed by device, kind, precision
 and a size class of the sweep, so a later process reuses them without
 re-timing.
@@ -26,6 +27,7 @@ RUNS_PER_LANE = (1, 2, 4, 6, 8, 12, 16, 32)
 STEPS_PER_SYNC = (2, 4, 8, 12, 16, 32)
 RUNS_PER_WAVE = (1, 2, 4, 8, 16, 32, 64)  # DDM, one wavefront per run
 WAVES_PER_SIMD = (0, 4, 8)  # 0: the compiler's register allocation
+BLOCKS = (256, 512, 1024)  # threads per workgroup of the lane kernels
 
 
 def size_class(w):
@@ -70,50 +72,61 @@ def default_candidates(w):
 def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=3):
     """Time every candidate shape on workload ``w`` (a workload dict, or a list
     of workloads of one kind and precision timed as one batched launch);
-    install and return the best as (tuning dict, kernel ms, table of
-    (rpl, sps, lpr, ms), then (rpl, sps, lpr, ms, waves cap) for the
-    occupancy variants of the best shape).  Shapes within a few per cent of each other are
-    not told apart by one timing, so the ``finalists`` fastest are timed
-    ``rounds`` more times and ranked by their fastest timing."""
+    install and return the best as (tuning dict, kernel ms, table).  Table
+    rows are (rpl, sps, lpr, ms, waves cap, block): first every candidate
+    shape in 256-thread workgroups, then, for the lane kernels, the best
+    shape in workgroups of 512 and 1024 threads (with as many and with half
+    as many runs per lane), then the register caps on the best of those.
+    Shapes within a few per cent of each other are not told apart by one
+    timing, so the ``finalists`` fastest are timed ``rounds`` more times and
+    ranked by their fastest timing."""
     ws = w if isinstance(w, list) else [w]
     w = ws[0]
     kind, prec = int(w["kind"]), int(w["precision"])
     ds = [cm.DeviceSweep(handle, x) for x in ws] if len(ws) > 1 else cm.DeviceSweep(handle, w)
     table = []
     cands = candidates or default_candidates(w)
+
+    def run(rpl, sps, lpr, waves=0, block=256, best_of=1):
+        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr,
+                          waves_per_simd=waves, block=block)
+        return min(time_shape(handle, ds, reps) for _ in range(best_of))
+
     for c in cands:
         rpl, sps = c[0], c[1]
         lpr = c[2] if len(c) > 2 else 1
-        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr)
-        ms = time_shape(handle, ds, reps)
-        table.append((rpl, sps, lpr, ms))
+        ms = run(rpl, sps, lpr)
+        table.append((rpl, sps, lpr, ms, 0, 256))
         if verbose:
             print(f"  runs/lane {rpl:3d} steps/sync {sps:3d} lanes/run {lpr:2d}: {ms:.4f} ms",
                   flush=True)
     table.sort(key=lambda r: r[3])
-    for i, (rpl, sps, lpr, ms) in enumerate(table[:finalists]):
-        handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr)
-        for _ in range(rounds):
-            ms = min(ms, time_shape(handle, ds, reps))
-        table[i] = (rpl, sps, lpr, ms)
-    rpl, sps, lpr, ms = min(table, key=lambda r: r[3])
-    # the occupancy axis, on the best shape: registers capped for 4 or 8
-    # wavefronts per SIMD against the compiler's own allocation
-    waves = 0
+    for i, (rpl, sps, lpr, ms, _, _) in enumerate(table[:finalists]):
+        ms = min(ms, run(rpl, sps, lpr, best_of=rounds))
+        table[i] = (rpl, sps, lpr, ms, 0, 256)
+    best = min(table, key=lambda r: r[3])
+    rpl, sps, lpr, ms, _, _ = best
     if kind in (0, 1) and lpr != 64:
-        best = ms
+        # workgroup size: a larger workgroup packs more unfinished runs
+        # together while its chunk drains, but holds more of a compute unit
+        for blk in BLOCKS[1:]:
+            for r in sorted({rpl, max(1, rpl // 2)}):
+                t = run(r, sps, lpr, block=blk, best_of=rounds)
+                table.append((r, sps, lpr, t, 0, blk))
+                if verbose:
+                    print(f"  block {blk} runs/lane {r}: {t:.4f} ms", flush=True)
+        best = min(table, key=lambda r: r[3])
+        # the occupancy axis, on the best shape: registers capped for 4 or 8
+        # wavefronts per SIMD against the compiler's own allocation
         for wv in WAVES_PER_SIMD[1:]:
-            handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps,
-                              lanes_per_run=lpr, waves_per_simd=wv)
-            t = min(time_shape(handle, ds, reps) for _ in range(rounds))
-            table.append((rpl, sps, lpr, t, wv))
+            t = run(best[0], sps, lpr, waves=wv, block=best[5], best_of=rounds)
+            table.append((best[0], sps, lpr, t, wv, best[5]))
             if verbose:
                 print(f"  waves/SIMD cap {wv}: {t:.4f} ms", flush=True)
-            if t < best:
-                best, waves = t, wv
-        ms = best
+        best = min(table, key=lambda r: r[3])
+    rpl, sps, lpr, ms, waves, block = best
     handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr,
-                      waves_per_simd=waves)
+                      waves_per_simd=waves, block=block)
     return handle.get_tuning(kind, prec), ms, table
 
 

@@ -375,11 +375,16 @@ struct TcSpec {
 // launch_runs: runs of every sweep in the same launch (sets the automatic
 // runs per lane, which trades GPU fill against the tail of each chunk).
 
+// Threads per workgroup of a lane-kernel launch: the tuned block; the
+// time-course variant is built for 256 only.
+uint32_t lane_block(const cm_tuning& t, bool timecourse) { return timecourse ? 256u : t.block; }
+
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
                     const Layout& L, uint32_t scan_block, uint64_t launch_runs, const TcSpec& tc,
                     cm::SimArgs& a, uint64_t& groups, size_t& lds) {
   const bool scan = scan_block != 0;
   const cm_tuning& tune = h->tune[m->kind][m->precision];
+  const uint32_t block = lane_block(tune, tc.every != 0);
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
   const uint32_t B = s->n_bins;
@@ -445,7 +450,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
     chunk = (uint64_t)waves * rpl;
   } else {
     if (!rpl) rpl = std::max<uint64_t>(2, std::min<uint64_t>(8, launch_runs / (4096ull * h->cu_count)));
-    chunk = (uint64_t)tune.block * rpl;
+    chunk = (uint64_t)block * rpl;
   }
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
   if (tc.every) {
@@ -465,14 +470,14 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   }
   const size_t rec_bytes = 4u * (cm::rec_words(B) + (tc.every ? cm::tc_words(a.tc_k) : 0u));
   // the lane kernel also stages its drain through LDS after the window
-  const size_t stage = scan ? 0 : cm::lane_stage_bytes((int)m->kind, (int)m->precision);
+  const size_t stage = scan ? 0 : cm::lane_stage_bytes((int)m->kind, (int)m->precision, block);
   const uint64_t wmax =
       std::min<size_t>(kLdsBudget, h->lds_per_block > stage ? h->lds_per_block - stage : 0) / rec_bytes;
   bool direct = false;
   // settings touched by one chunk: at most floor((chunk-1)/T) + 2
   if (wmax < 2 || (chunk - 1) / T + 2 > wmax) {
     const uint64_t fit = wmax >= 2 ? (wmax - 1) * T : 0;
-    if (fit >= std::min<uint64_t>(chunk, tune.block)) chunk = fit;
+    if (fit >= std::min<uint64_t>(chunk, block)) chunk = fit;
     else direct = true;
   }
   a.chunk = chunk;
@@ -481,6 +486,7 @@ cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm
   groups = (runs + chunk - 1) / chunk;
   lds = direct ? 0 : (size_t)a.window * rec_bytes;
   lds += stage;
+  if (lds > h->lds_per_block) return fail(CM_E_UNSUPPORTED, "lane kernel: LDS stage too large for this block size");
   return ok();
 }
 
@@ -713,7 +719,8 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
   ProfScope prof{h, stream, timed};
   if ((e = prof.begin()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_sim_lane((int)kind, (int)prec, scan_block, tc.every != 0,
-                               h->tune[kind][prec].waves_per_simd, b, lds, stream)) != hipSuccess)
+                               h->tune[kind][prec].waves_per_simd,
+                               lane_block(h->tune[kind][prec], tc.every != 0), b, lds, stream)) != hipSuccess)
     return hip_fail(e, "simulation kernel");
   if ((e = prof.end()) != hipSuccess) return hip_fail(e, "hipEventRecord");
   if ((e = cm::launch_score(sb, stream)) != hipSuccess) return hip_fail(e, "score kernel");
@@ -903,7 +910,8 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
   if (!v.tile_rows) v.tile_rows = d.tile_rows;
   if (v.lanes_per_run != 0 && v.lanes_per_run != 1 && !(kind == CM_DDM && v.lanes_per_run == 64))
     return fail(CM_E_INVALID, "lanes_per_run must be 0, 1 (or 64 for the DDM)");
-  if (v.block != 256) return fail(CM_E_UNSUPPORTED, "block must be 256");
+  if (v.block != 256 && !((kind == CM_DDM || kind == CM_CONFLICT_LCA) && (v.block == 512 || v.block == 1024)))
+    return fail(CM_E_UNSUPPORTED, "block must be 256, or 512 or 1024 for the DDM and conflict-LCA lane kernels");
   if (v.runs_per_lane > 4096) return fail(CM_E_INVALID, "runs_per_lane must be <= 4096");
   if (v.steps_per_sync < 1 || v.steps_per_sync > 64) return fail(CM_E_INVALID, "steps_per_sync must be in [1, 64]");
   if (v.tile_rows != 16) return fail(CM_E_UNSUPPORTED, "tile_rows must be 16");

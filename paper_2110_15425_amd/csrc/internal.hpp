@@ -190,14 +190,16 @@ struct DensityArgs {
 // threads (256 or 512) per workgroup.
 // occ: 0, or 4 / 8 for the lane kernel built with registers capped so that
 // that many wavefronts fit per SIMD (ignored by the scan kernel).
+// block: threads per workgroup of the lane kernel, 256, 512 or 1024 (256
+// for the time-course variant; ignored by the scan kernel).
 hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, uint32_t occ,
-                           const LaneBatch& b, size_t lds_bytes, hipStream_t st);
+                           uint32_t block, const LaneBatch& b, size_t lds_bytes, hipStream_t st);
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
                           double* out, hipStream_t st);
 // LDS after the histogram window (and the time-course blocks) that the lane
 // kernel uses to pack unfinished runs while a chunk drains.
-size_t lane_stage_bytes(int kind, int precision);
+size_t lane_stage_bytes(int kind, int precision, uint32_t block);
 hipError_t launch_score(const ScoreBatch& b, hipStream_t st);
 uint32_t loop_team_lanes(uint32_t J, uint64_t runs, uint32_t cus);
 hipError_t launch_loop(int precision, const LoopArgs& a, uint32_t team, uint32_t blocks, hipStream_t st);

@@ -545,8 +545,8 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
 // registers so that that many wavefronts fit on each SIMD (the register use
 // versus occupancy trade-off of the paper's GPU study, Sec. 6.3; a cap below
 // the kernel's natural use spills or recomputes values).
-template <class M, bool TC, int OCC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1)))
+template <class M, bool TC, int OCC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1)))
 void sim_lane_kernel(LaneBatch batch) {
   extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
   uint32_t* lds = (uint32_t*)lds_u64;
@@ -583,7 +583,7 @@ void sim_lane_kernel(LaneBatch batch) {
   Lane L;
   uint32_t off = threadIdx.x;
   bool have = off < len;
-  __shared__ uint32_t drain_cnt[kBlock / 64];
+  __shared__ uint32_t drain_cnt[BLOCK / 64];
   auto setup = [&](uint32_t o) {
     const uint32_t local = t_lo + o;  // < 2^31 + chunk
     L.s = s_lo + udiv_magic(local, a.trials_magic);
@@ -621,7 +621,7 @@ void sim_lane_kernel(LaneBatch batch) {
   // leaves their issue slots to the other workgroups on the compute unit
   // instead of stepping a few live lanes each.
   M* stage_m = (M*)(lds + a.window * (rec_words(a.n_bins) + (TC ? tc_words(a.tc_k) : 0u)));
-  LaneWords* stage_l = (LaneWords*)(stage_m + kBlock);
+  LaneWords* stage_l = (LaneWords*)(stage_m + BLOCK);
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   const uint64_t below = (1ull << lane) - 1ull;
   for (;;) {
@@ -630,7 +630,7 @@ void sim_lane_kernel(LaneBatch batch) {
     if (lane == 0) drain_cnt[w] = (uint32_t)__popcll(act);
     __syncthreads();
     uint32_t base = 0, total = 0;
-    for (uint32_t v = 0; v < kBlock / 64; ++v) {
+    for (uint32_t v = 0; v < BLOCK / 64; ++v) {
       if (v < w) base += drain_cnt[v];
       total += drain_cnt[v];
     }
@@ -802,25 +802,37 @@ __global__ __launch_bounds__(kBlock) void ceiling_kernel(SimArgs a, uint32_t ste
   out[g] = st[0];
 }
 
-template <class M>
-hipError_t launch_model(const LaneBatch& b, bool tc, uint32_t occ, size_t lds, hipStream_t st) {
-  const dim3 grid(b.base[b.n]), block(kBlock);
-  if (tc)
-    hipLaunchKernelGGL((sim_lane_kernel<M, true, 0>), grid, block, lds, st, b);
-  else if (occ == 4)
-    hipLaunchKernelGGL((sim_lane_kernel<M, false, 4>), grid, block, lds, st, b);
+template <class M, int BLOCK>
+void launch_occ(const LaneBatch& b, uint32_t occ, size_t lds, hipStream_t st) {
+  const dim3 grid(b.base[b.n]), block(BLOCK);
+  if (occ == 4)
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 4, BLOCK>), grid, block, lds, st, b);
   else if (occ == 8)
-    hipLaunchKernelGGL((sim_lane_kernel<M, false, 8>), grid, block, lds, st, b);
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 8, BLOCK>), grid, block, lds, st, b);
   else
-    hipLaunchKernelGGL((sim_lane_kernel<M, false, 0>), grid, block, lds, st, b);
+    hipLaunchKernelGGL((sim_lane_kernel<M, false, 0, BLOCK>), grid, block, lds, st, b);
+}
+
+template <class M>
+hipError_t launch_model(const LaneBatch& b, bool tc, uint32_t occ, uint32_t block, size_t lds,
+                        hipStream_t st) {
+  if (tc)
+    hipLaunchKernelGGL((sim_lane_kernel<M, true, 0, kBlock>), dim3(b.base[b.n]), dim3(kBlock), lds, st, b);
+  else if (block == 512)
+    launch_occ<M, 512>(b, occ, lds, st);
+  else if (block == 1024)
+    launch_occ<M, 1024>(b, occ, lds, st);
+  else
+    launch_occ<M, kBlock>(b, occ, lds, st);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc, uint32_t occ,
-                           const LaneBatch& b, size_t lds_bytes, hipStream_t st) {
-  if (b.n < 1 || b.n > kMaxBatch || (scan_block && tc) || (occ && occ != 4 && occ != 8))
+                           uint32_t block, const LaneBatch& b, size_t lds_bytes, hipStream_t st) {
+  if (b.n < 1 || b.n > kMaxBatch || (scan_block && tc) || (occ && occ != 4 && occ != 8) ||
+      (block != 256 && block != 512 && block != 1024) || (tc && block != (uint32_t)kBlock))
     return hipErrorInvalidValue;
   if (scan_block) {
     if (kind != CM_DDM || (scan_block != 256u && scan_block != (uint32_t)kScanBlockMax))
@@ -832,17 +844,17 @@ hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc
     return hipGetLastError();
   }
   if (kind == CM_DDM)
-    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, tc, occ, lds_bytes, st)
-                                : launch_model<DDM<CM_FP32_STEP>>(b, tc, occ, lds_bytes, st);
-  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, occ, lds_bytes, st)
-                              : launch_model<LCA<CM_FP32_STEP>>(b, tc, occ, lds_bytes, st);
+    return precision == CM_FP64 ? launch_model<DDM<CM_FP64>>(b, tc, occ, block, lds_bytes, st)
+                                : launch_model<DDM<CM_FP32_STEP>>(b, tc, occ, block, lds_bytes, st);
+  return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, occ, block, lds_bytes, st)
+                              : launch_model<LCA<CM_FP32_STEP>>(b, tc, occ, block, lds_bytes, st);
 }
 
-size_t lane_stage_bytes(int kind, int precision) {
+size_t lane_stage_bytes(int kind, int precision, uint32_t block) {
   size_t m;
   if (kind == CM_DDM) m = precision == CM_FP64 ? sizeof(DDM<CM_FP64>) : sizeof(DDM<CM_FP32_STEP>);
   else m = precision == CM_FP64 ? sizeof(LCA<CM_FP64>) : sizeof(LCA<CM_FP32_STEP>);
-  return (size_t)kBlock * (m + sizeof(LaneWords));
+  return (size_t)block * (m + sizeof(LaneWords));
 }
 
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,

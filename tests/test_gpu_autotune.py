@@ -18,18 +18,24 @@ def test_tune_installs_the_fastest_listed_shape():
     w = W.conflict(trials=400, precision=W.FP32_STEP)
     before = cm.run(w, handle=h)
     t, ms, table = autotune.tune(h, w, reps=2, candidates=CANDS, finalists=2, rounds=2)
-    shapes = [r for r in table if len(r) == 4]
-    caps = [r for r in table if len(r) == 5]
-    assert len(shapes) == len(CANDS)
+    assert all(len(r) == 6 for r in table)
+    shapes = table[:len(CANDS)]
+    assert all(r[4:] == (0, 256) for r in shapes)
     assert {(r[0], r[1]) for r in shapes} == set(CANDS)
     best = min(shapes, key=lambda r: r[3])
-    assert (t["runs_per_lane"], t["steps_per_sync"]) == (best[0], best[1])
-    # the occupancy axis: the register caps timed on the best shape
+    # the workgroup-size axis on the best shape, with its runs per lane and half
+    blocks = [r for r in table[len(CANDS):] if r[4] == 0]
+    assert {r[5] for r in blocks} == {512, 1024}
+    assert all(r[1] == best[1] and r[0] in (best[0], max(1, best[0] // 2)) for r in blocks)
+    # the occupancy axis: the register caps timed on the best of those
+    caps = [r for r in table if r[4] != 0]
     assert [r[4] for r in caps] == [4, 8]
-    assert all((r[0], r[1]) == (best[0], best[1]) for r in caps)
-    fastest = min([best[3]] + [r[3] for r in caps])
-    assert ms == fastest > 0
-    assert t["waves_per_simd"] in (0, 4, 8)
+    lead = min(shapes + blocks, key=lambda r: r[3])
+    assert all((r[0], r[1], r[5]) == (lead[0], lead[1], lead[5]) for r in caps)
+    fastest = min(table, key=lambda r: r[3])
+    assert ms == fastest[3] > 0
+    assert (t["runs_per_lane"], t["steps_per_sync"], t["waves_per_simd"], t["block"]) == \
+        (fastest[0], fastest[1], fastest[4], fastest[5])
     assert h.get_tuning(W.LCA, W.FP32_STEP) == t
     after = cm.run(w, handle=h)
     for k in ("hist", "stats"):
@@ -101,6 +107,51 @@ def test_register_caps_leave_results_unchanged(kind):
         correct = oracle.conflict_correct(w["weights"], w["params"][W.LCA_P["hid_gain"]],
                                           w["params"][W.LCA_P["hid_bias"]])
     assert_parity(w, outs[2], orc, correct)
+
+
+@pytest.mark.parametrize("kind,prec", [("lca", W.FP64), ("lca", W.FP32_STEP), ("ddm", W.FP64)])
+def test_workgroup_sizes_leave_results_unchanged(kind, prec):
+    """Lane kernels in workgroups of 512 and 1024 threads (one drain packing
+    over more wavefronts; several sweeps in one launch) compute per run
+    exactly what 256-thread workgroups compute, and match the oracle (FP64)."""
+    import oracle
+    from parity import assert_parity
+    h = cm.Handle(0)
+    if kind == "lca":
+        ws = [W.conflict(trials=900, grid=W.control_grid(6)[::3], reward=1.0, cost=0.1, seed=s,
+                         precision=prec) for s in (31, 32)]
+        k = W.LCA
+    else:
+        ws = [W.ddm(trials=3000, drifts=np.linspace(-0.3, 0.5, 5), seed=s) for s in (33, 34)]
+        k = W.DDM
+    outs = []
+    for blk in (256, 512, 1024):
+        h.set_tuning(k, prec, block=blk, runs_per_lane=3, lanes_per_run=1 if kind == "ddm" else 0)
+        assert h.get_tuning(k, prec)["block"] == blk
+        outs.append([cm.run(w, dumps=True, handle=h) for w in ws])
+        ds = [cm.DeviceSweep(h, w) for w in ws]
+        cm.launch_batch(h, ds)
+        outs[-1].append([d.results() for d in ds])
+    for o in outs[1:]:
+        for i in range(2):
+            for key in ("hist", "stats", "run_choice", "run_step", "run_flag", "run_state"):
+                assert np.array_equal(outs[0][i][key], o[i][key]), (i, key)
+            for key in ("hist", "stats"):
+                assert np.array_equal(outs[0][i][key], o[2][i][key]), ("batch", i, key)
+    if prec == W.FP64:
+        correct = [1]
+        if kind == "lca":
+            correct = oracle.conflict_correct(ws[0]["weights"], ws[0]["params"][W.LCA_P["hid_gain"]],
+                                              ws[0]["params"][W.LCA_P["hid_bias"]])
+        assert_parity(ws[0], outs[2][0], oracle.run(ws[0], dumps=True), correct)
+
+
+def test_workgroup_size_rejected_where_not_built():
+    h = cm.Handle(0)
+    for k, p in ((W.LCA, W.FP64), (W.RNN, W.BF16_PROJ)):
+        with pytest.raises(cm.CmError) as e:
+            h.set_tuning(k, p, block=768 if k == W.LCA else 512)
+        assert e.value.status == cm.E_UNSUPPORTED
 
 
 def test_register_cap_rejected_where_not_built():
