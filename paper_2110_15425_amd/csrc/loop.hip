@@ -45,6 +45,56 @@ namespace {
 constexpr int kLoopBlock = 256;
 constexpr int kLoopChains = 4;  // allocations a lane of a wide search evaluates together
 constexpr uint32_t kStreamLook = 0x80000000u;  // | (allocation * M + sample)
+
+// Philox4x32-10 on the counter (k, t, s, c3) with many stream words c3 at one
+// step k of one run (the closed loop's look-ahead samples): the work that
+// depends only on (k, t, s) -- round 1 but for c3's xor, round 2's product
+// with the constant c0, round 3's product with the constant c2 -- is done
+// once per step.  The words equal philox(k, t, s, c3, k0, k1) bit for bit.
+
+struct StreamKey {
+  uint32_t e2;  // round 1: hi(M0 k) ^ k1, xored with c3
+  uint32_t b1;  // round 2: lo(M1 s) ^ (k0 + W0), xored with hi(M1 c2)
+  uint32_t g1;  // round 3: hi(M1 c2'') ^ (k0 + 2 W0), xored with round 2's lo(M1 c2)
+  uint32_t l1;  // round 3: lo(M1 c2''), the new c1
+  uint32_t d3;  // round 3: lo(M0 c0') ^ (k1 + 2 W1), xored with hi(M0 c0'')
+};
+
+__device__ __forceinline__ StreamKey stream_key(uint32_t k, uint32_t t, uint32_t s, uint32_t k0,
+                                                uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kPhiloxM0 * k, p1 = (uint64_t)kPhiloxM1 * s;
+  const uint32_t c0 = (uint32_t)(p1 >> 32) ^ t ^ k0;  // round 1's c0, c1 and c3
+  const uint32_t c1 = (uint32_t)p1, c3 = (uint32_t)p0;
+  const uint64_t q0 = (uint64_t)kPhiloxM0 * c0;  // round 2's c2 and c3
+  const uint32_t c2b = (uint32_t)(q0 >> 32) ^ c3 ^ (k1 + kPhiloxW1);
+  const uint64_t u1 = (uint64_t)kPhiloxM1 * c2b;
+  StreamKey r;
+  r.e2 = (uint32_t)(p0 >> 32) ^ k1;
+  r.b1 = c1 ^ (k0 + kPhiloxW0);
+  r.g1 = (uint32_t)(u1 >> 32) ^ (k0 + 2u * kPhiloxW0);
+  r.l1 = (uint32_t)u1;
+  r.d3 = (uint32_t)q0 ^ (k1 + 2u * kPhiloxW1);
+  return r;
+}
+
+__device__ __forceinline__ Words philox_stream(const StreamKey& r, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+  const uint64_t q1 = (uint64_t)kPhiloxM1 * (r.e2 ^ c3);  // round 2, lane part
+  const uint64_t u0 = (uint64_t)kPhiloxM0 * ((uint32_t)(q1 >> 32) ^ r.b1);  // round 3
+  uint32_t c0 = (uint32_t)q1 ^ r.g1, c1 = r.l1;
+  uint32_t c2 = (uint32_t)(u0 >> 32) ^ r.d3, c3n = (uint32_t)u0;
+#pragma unroll
+  for (uint32_t round = 3; round < 10; ++round) {
+    const uint64_t v0 = (uint64_t)kPhiloxM0 * c0, v1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t m0 = xor3((uint32_t)(v1 >> 32), c1, k0 + round * kPhiloxW0);
+    const uint32_t m2 = xor3((uint32_t)(v0 >> 32), c3n, k1 + round * kPhiloxW1);
+    c1 = (uint32_t)v1;
+    c3n = (uint32_t)v0;
+    c0 = m0;
+    c2 = m2;
+  }
+  return Words{c0, c1, c2, c3n};
+}
 constexpr uint32_t kStreamPick = 0xC0000000u;  // | allocation
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -200,6 +250,8 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
         }
       }
       const double dx = c ? x1 - x0 : x0 - x1;  // x_c - x_w
+      // the look-ahead blocks of this step differ only in their stream word
+      const StreamKey sk = stream_key(k, t, s, k0, k1);
       double bv = INFINITY, sv = INFINITY;
       uint32_t bj = kNone;
       // A lane's allocations j0, j0 + P, ... are evaluated U at a time, so
@@ -226,7 +278,7 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
         for (uint32_t m = 0; m < M; ++m) {
 #pragma unroll
           for (uint32_t u = 0; u < U; ++u) {
-            const Words w = philox(k, t, s, kStreamLook | (ju[u] * M + m), k0, k1);
+            const Words w = philox_stream(sk, kStreamLook | (ju[u] * M + m), k0, k1);
             double y0, y1;
             if constexpr (P == 64)
               lca_step<PREC>(a, x0, x1, i0[u], i1[u], f0[u], f1[u], w, y0, y1);
@@ -240,7 +292,15 @@ __global__ __launch_bounds__(kLoopBlock) void loop_kernel(LoopArgs a) {
         for (uint32_t u = 0; u < U; ++u) {
           if (j + u * P >= J) break;
           const uint32_t jj = ju[u];
-          const double mean = pow2 ? gs[u] * inv_m : gs[u] / (double)M;
+          double mean;
+          if (pow2) {
+            mean = gs[u] * inv_m;
+          } else {
+            // a branch of its own: the division is not evaluated beside the
+            // product when M is a power of two
+            asm volatile("" ::: "memory");
+            mean = gs[u] / (double)M;
+          }
           const double V = kappa * a.norm2[jj] - mean;
           if (V < bv) {
             sv = bv;
