@@ -175,16 +175,53 @@ __device__ __forceinline__ double read_lane(double v, int src) {
   return __longlong_as_double((long long)((uint64_t)lo | ((uint64_t)hi << 32)));
 }
 
+// The two halves of the wavefront's 16-lane row pairs (R = 4: rows 0|1 and
+// 2|3) or of its 32-lane halves (R = 5), lane by lane: gfx950's row swaps
+// between two copies of a register (the odd rows, or the upper half, of one
+// copy trade places with the even rows, or the lower half, of the other)
+// leave one half's values in one result and the other's in the other, in
+// every lane of the pair (which is which does not matter to a minimum).
+template <int R>
+__device__ __forceinline__ void halves(uint32_t v, uint32_t& a, uint32_t& b) {
+  if constexpr (R == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = r[0];
+    b = r[1];
+  }
+}
+template <int R>
+__device__ __forceinline__ double halves_min(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  uint32_t la, lb, ha, hb;
+  halves<R>((uint32_t)u, la, lb);
+  halves<R>((uint32_t)(u >> 32), ha, hb);
+  return fmin(__longlong_as_double((long long)((uint64_t)la | ((uint64_t)ha << 32))),
+              __longlong_as_double((long long)((uint64_t)lb | ((uint64_t)hb << 32))));
+}
+template <int R>
+__device__ __forceinline__ uint64_t halves_min(uint64_t v) {
+  uint32_t la, lb, ha, hb;
+  halves<R>((uint32_t)v, la, lb);
+  halves<R>((uint32_t)(v >> 32), ha, hb);
+  const uint64_t a = (uint64_t)la | ((uint64_t)ha << 32), b = (uint64_t)lb | ((uint64_t)hb << 32);
+  return a < b ? a : b;
+}
+
 // Minimum over the wavefront, the same value in every lane (all lanes
-// active; NaN loses to any number, as the scan's comparisons ignore it).
+// active; NaN loses to any number, as the scan's comparisons ignore it):
+// rounds 0-3 within rows by DPP, then the row pairs and the two halves by
+// row swaps (no LDS round trip).
 __device__ __forceinline__ double wave_min(double v) {
   v = fmin(v, partner<0>(v));
   v = fmin(v, partner<1>(v));
   v = fmin(v, partner<2>(v));
   v = fmin(v, partner<3>(v));
-  v = fmin(v, partner<4>(v));
-  v = fmin(v, partner<5>(v));
-  return v;
+  v = halves_min<4>(v);
+  return halves_min<5>(v);
 }
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   auto step = [&](auto round) {
@@ -196,9 +233,8 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   step(std::integral_constant<int, 1>{});
   step(std::integral_constant<int, 2>{});
   step(std::integral_constant<int, 3>{});
-  step(std::integral_constant<int, 4>{});
-  step(std::integral_constant<int, 5>{});
-  return v;
+  v = halves_min<4>(v);
+  return halves_min<5>(v);
 }
 
 template <int PREC, int P, int U>
