@@ -222,6 +222,25 @@ def time_mode(h, ds, steps, warmup):
     return wall_ms, sim_ms / max(n, 1)
 
 
+def time_graph(h, ds, steps, warmup):
+    """Wall milliseconds of `steps` replays of the batched launch of ``ds``
+    from the handle's graph cache (the first warm-up call captures it)."""
+    import torch
+
+    from paper_2110_15425_amd import cm
+    for _ in range(max(1, warmup)):
+        cm.launch_graph(h, ds)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        cm.launch_graph(h, ds)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def rate_network(cm, W):
     """The 256-unit rate network, 65,536 runs: bf16 projections vs FP64."""
     import torch
@@ -328,6 +347,7 @@ def main():
               "(a sweep would shard by contiguous run ranges, one per GPU, with an "
               "all-reduce of the integer outputs)", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     from paper_2110_15425_amd import cm, workloads as W
 
@@ -388,6 +408,16 @@ def main():
                             rate=rs * args.steps / (wall_ms / 1e3))
     print(f"# fp32 batched x{BATCH}: {wall_ms / args.steps:.4f} ms/step, simulation kernel "
           f"{kern_ms:.4f} ms, {rs} run-steps/step", file=sys.stderr, flush=True)
+    # the same batched step replayed from the handle's graph cache; its
+    # outputs must equal the eager launches'
+    dsg = [cm.DeviceSweep(h_tuned, w) for w in wb]
+    g_wall = time_graph(h_tuned, dsg, args.steps, args.warmup)
+    g_same = all(np.array_equal(a.results()[k], b.results()[k])
+                 for a, b in zip(dsg, dsb) for k in ("hist", "stats", "score", "best"))
+    res["fp32_graph"] = dict(run_steps=rs, wall_ms=g_wall, rate=rs * args.steps / (g_wall / 1e3),
+                             same=g_same)
+    print(f"# fp32 batched x{BATCH} from a graph: {g_wall / args.steps:.4f} ms/step, "
+          f"results {'equal' if g_same else 'DIFFERENT'}", file=sys.stderr, flush=True)
 
     head = res["fp32_step"]
     ach = head["run_steps"] * LANE_OPS_PER_STEP["fp32_step"] / (head["kern_ms"] / 1e3)
@@ -419,6 +449,9 @@ def main():
         "fp32_single_sweep": {"value": res["fp32_single"]["rate"],
                               "ms_per_step": res["fp32_single"]["wall_ms"] / args.steps,
                               "kernel_ms": res["fp32_single"]["kern_ms"]},
+        "fp32_batched_graph": {"value": res["fp32_graph"]["rate"],
+                               "ms_per_step": res["fp32_graph"]["wall_ms"] / args.steps,
+                               "results_equal_eager": res["fp32_graph"]["same"]},
         "fp64_plain": {"value": res["fp64"]["rate"],
                        "ms_per_step": res["fp64"]["wall_ms"] / args.steps,
                        "kernel_ms": res["fp64"]["kern_ms"]},

@@ -294,6 +294,28 @@ cm_status cm_launch_batch(cm_handle *h, uint32_t n, const cm_model *models,
                           void *const *workspaces, const uint64_t *workspace_bytes,
                           void *hip_stream);
 
+/* cm_launch_batch replayed from a HIP graph the handle keeps: the first call
+ * with a given argument set captures the batch's launches on a stream of the
+ * library's own and instantiates them; a later call whose arguments are all
+ * equal -- every struct field, every pointer, the parameter values behind
+ * `params`, and the handle's tuning -- launches that graph on hip_stream, one
+ * launch instead of a preparation, simulation and score launch per group
+ * (the batching of many evaluations into few launches, Sec. 3.6, carried to
+ * the launch sequence itself).  Results are those of cm_launch_batch: the
+ * graph re-zeroes the outputs with its preparation kernels, never with
+ * memset nodes.  A graph holds the buffers' addresses, so its entry must not
+ * be replayed after the buffers are freed; cm_graph_clear drops every graph,
+ * and at most CM_GRAPH_CACHE are kept (the least recently used goes first).
+ * The graph is launched untimed (cm_profile sees no simulation launch).
+ * Errors as for cm_launch_batch, or CM_E_DEVICE when capture, instantiation
+ * or the graph launch fails. */
+#define CM_GRAPH_CACHE 16u
+cm_status cm_launch_graph(cm_handle *h, uint32_t n, const cm_model *models,
+                          const cm_sweep *sweeps, const cm_result *results,
+                          void *const *workspaces, const uint64_t *workspace_bytes,
+                          void *hip_stream);
+cm_status cm_graph_clear(cm_handle *h);
+
 /* Time course: what cm_launch computes, plus ensemble statistics of the state
  * over time -- the dynamics modellers study beside final outcomes (Distill,
  * Sec. 1 and 2.1), including the conflict energy of the two mutually

@@ -25,7 +25,8 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
-           "cm_get_tuning", "cm_launch", "cm_launch_scratch", "cm_launch_batch", "cm_launch_timecourse",
+           "cm_get_tuning", "cm_launch", "cm_launch_scratch", "cm_launch_batch", "cm_launch_graph",
+           "cm_graph_clear", "cm_launch_timecourse",
            "cm_unfused_workspace_bytes",
            "cm_launch_unfused", "cm_ddm_density", "cm_serve_config", "cm_submit", "cm_poll",
            "cm_ceiling",
@@ -92,6 +93,10 @@ def lib():
         L.cm_launch_batch.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
                                       C.POINTER(Result), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_uint64), C.c_void_p]
+        L.cm_launch_graph.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(Model), C.POINTER(Sweep),
+                                      C.POINTER(Result), C.POINTER(C.c_void_p),
+                                      C.POINTER(C.c_uint64), C.c_void_p]
+        L.cm_graph_clear.argtypes = [C.c_void_p]
         L.cm_launch_timecourse.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep),
                                            C.POINTER(Result), C.c_uint32, C.c_void_p, C.c_void_p,
                                            C.c_uint64, C.c_void_p]
@@ -308,6 +313,26 @@ def launch_batch(handle, sweeps, stream=None):
     wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
     wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
     check(lib().cm_launch_batch(handle.h, n, models, sws, res, wsp, wsb, C.c_void_p(st.cuda_stream)))
+
+
+def launch_graph(handle, sweeps, stream=None):
+    """Enqueue several DeviceSweeps as cm_launch_batch would, replayed from the
+    handle's graph cache (cm_launch_graph): captured on the first call with
+    these exact arguments, launched as one graph afterwards."""
+    import torch
+    n = len(sweeps)
+    st = stream if stream is not None else torch.cuda.current_stream(handle.device)
+    models = (Model * n)(*[d.model for d in sweeps])
+    sws = (Sweep * n)(*[d.sweep for d in sweeps])
+    res = (Result * n)(*[d.result for d in sweeps])
+    wsp = (C.c_void_p * n)(*[d.workspace.data_ptr() for d in sweeps])
+    wsb = (C.c_uint64 * n)(*[d.workspace.numel() for d in sweeps])
+    check(lib().cm_launch_graph(handle.h, n, models, sws, res, wsp, wsb, C.c_void_p(st.cuda_stream)))
+
+
+def graph_clear(handle):
+    """Drop every graph the handle keeps (cm_graph_clear)."""
+    check(lib().cm_graph_clear(handle.h))
 
 
 def serve_config(handle, n_slots):

@@ -37,7 +37,22 @@ struct cm_handle {
   };
   std::vector<Slot> slots;
   uint64_t next_ticket = 1;
+  // graph cache of cm_launch_graph: instantiated graphs keyed by the whole
+  // argument set (see graph_signature), least recently used dropped first
+  struct Graph {
+    std::vector<uint64_t> sig;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last = 0;
+  };
+  std::vector<Graph> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t capture = nullptr;  // the library's own stream for captures
 };
+
+static void clear_graphs(cm_handle* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
 
 // Workspace of cm_launch_scratch: one array per device, living as long as
 // the process.  In host code `scratch` names a host-side stand-in, not the
@@ -776,6 +791,8 @@ cm_status cm_destroy(cm_handle* h) {
   if (h) {
     DeviceGuard guard(h->device);
     release_slots(h);
+    clear_graphs(h);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
   }
   if (h && h->host_count) (void)hipHostFree(h->host_count);
   if (h) {
@@ -1014,13 +1031,15 @@ cm_status cm_ceiling(cm_handle* h, const cm_model* m, uint32_t steps, uint64_t l
   return e == hipSuccess ? ok() : hip_fail(e, "ceiling kernel");
 }
 
-cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
-                          const cm_result* results, void* const* workspaces,
-                          const uint64_t* workspace_bytes, void* hip_stream) {
-  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+}  // extern "C"
+
+namespace {
+
+cm_status check_batch(uint32_t n, const cm_model* models, const cm_sweep* sweeps, const cm_result* results,
+                      void* const* workspaces, const uint64_t* workspace_bytes, std::vector<Layout>& L) {
   if (n < 1 || !models || !sweeps || !results || !workspaces || !workspace_bytes)
     return fail(CM_E_INVALID, "batch needs n >= 1 and non-NULL arrays");
-  std::vector<Layout> L(n);
+  L.assign(n, Layout{});
   for (uint32_t i = 0; i < n; ++i) {
     cm_status st = check_launch(&models[i], &sweeps[i], &results[i], workspaces[i], workspace_bytes[i], L[i]);
     if (st != CM_OK) {
@@ -1028,8 +1047,13 @@ cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, cons
       return st;
     }
   }
-  hipStream_t stream = (hipStream_t)hip_stream;
-  DeviceGuard guard(h->device);
+  return ok();
+}
+
+// The launches of a checked batch, enqueued on `stream` (current device set).
+cm_status enqueue_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
+                        const cm_result* results, void* const* workspaces, const std::vector<Layout>& L,
+                        hipStream_t stream) {
   // rate-network sweeps launch one by one; lane-kernel sweeps of one kind and
   // precision share launches of up to kMaxBatch sweeps
   std::vector<uint32_t> group;
@@ -1066,6 +1090,132 @@ cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, cons
         }
       }
     }
+  return ok();
+}
+
+// Everything a batched launch reads on the host: every field of every entry
+// (pointers as addresses), the parameter values behind `params`, the
+// handle's tuning and its device.  Two calls with equal signatures enqueue
+// the same kernels with the same arguments.
+std::vector<uint64_t> graph_signature(const cm_handle* h, uint32_t n, const cm_model* models,
+                                      const cm_sweep* sweeps, const cm_result* results,
+                                      void* const* workspaces, const uint64_t* workspace_bytes) {
+  std::vector<uint64_t> v;
+  auto put = [&](uint64_t x) { v.push_back(x); };
+  auto putd = [&](double x) {
+    uint64_t u;
+    memcpy(&u, &x, sizeof u);
+    v.push_back(u);
+  };
+  put((uint64_t)h->device);
+  for (uint32_t k = 0; k < 4; ++k)
+    for (uint32_t p = 0; p < 3; ++p) {
+      const cm_tuning& t = h->tune[k][p];
+      put(((uint64_t)t.block << 32) | t.runs_per_lane);
+      put(((uint64_t)t.steps_per_sync << 32) | t.tile_rows);
+      put(((uint64_t)t.lanes_per_run << 32) | t.waves_per_simd);
+    }
+  put(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const cm_model& m = models[i];
+    put(((uint64_t)m.abi_version << 32) | m.kind);
+    put(((uint64_t)m.precision << 32) | m.n_units);
+    put(((uint64_t)m.n_stimuli << 32) | m.n_signals);
+    put(m.n_params);
+    for (uint32_t k = 0; k < m.n_params; ++k) putd(m.params[k]);
+    put((uint64_t)(uintptr_t)m.weights);
+    put(m.n_weights);
+    const cm_sweep& sw = sweeps[i];
+    put((uint64_t)(uintptr_t)sw.grid);
+    put(sw.n_settings);
+    put(sw.trials);
+    put(sw.seed);
+    put(((uint64_t)sw.max_steps << 32) | sw.n_bins);
+    putd(sw.reward);
+    putd(sw.cost);
+    putd(sw.flag_eps);
+    const cm_result& r = results[i];
+    for (const void* q : {(const void*)r.hist, (const void*)r.stats, (const void*)r.score, (const void*)r.best,
+                          (const void*)r.run_choice, (const void*)r.run_step, (const void*)r.run_flag,
+                          (const void*)r.run_state})
+      put((uint64_t)(uintptr_t)q);
+    put((uint64_t)(uintptr_t)workspaces[i]);
+    put(workspace_bytes[i]);
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_launch_batch(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
+                          const cm_result* results, void* const* workspaces,
+                          const uint64_t* workspace_bytes, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  std::vector<Layout> L;
+  cm_status st = check_batch(n, models, sweeps, results, workspaces, workspace_bytes, L);
+  if (st != CM_OK) return st;
+  DeviceGuard guard(h->device);
+  return enqueue_batch(h, n, models, sweeps, results, workspaces, L, (hipStream_t)hip_stream);
+}
+
+cm_status cm_launch_graph(cm_handle* h, uint32_t n, const cm_model* models, const cm_sweep* sweeps,
+                          const cm_result* results, void* const* workspaces,
+                          const uint64_t* workspace_bytes, void* hip_stream) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  std::vector<Layout> L;
+  cm_status st = check_batch(n, models, sweeps, results, workspaces, workspace_bytes, L);
+  if (st != CM_OK) return st;
+  DeviceGuard guard(h->device);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<uint64_t> sig = graph_signature(h, n, models, sweeps, results, workspaces, workspace_bytes);
+  hipError_t e;
+  for (auto& g : h->graphs)
+    if (g.sig == sig) {
+      g.last = ++h->graph_clock;
+      if ((e = hipGraphLaunch(g.exec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      return ok();
+    }
+  // capture the batch's launches on the library's own stream (untimed: no
+  // events enter the graph) and keep the instantiated graph
+  if (!h->capture && (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  if ((e = hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "hipStreamBeginCapture");
+  const bool prof = h->prof;
+  h->prof = false;
+  st = enqueue_batch(h, n, models, sweeps, results, workspaces, L, h->capture);
+  h->prof = prof;
+  const std::string err = g_err;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(h->capture, &graph);
+  if (st != CM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    g_err = err;
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (h->graphs.size() >= CM_GRAPH_CACHE) {
+    size_t lru = 0;
+    for (size_t i = 1; i < h->graphs.size(); ++i)
+      if (h->graphs[i].last < h->graphs[lru].last) lru = i;
+    (void)hipGraphExecDestroy(h->graphs[lru].exec);
+    h->graphs.erase(h->graphs.begin() + (ptrdiff_t)lru);
+  }
+  h->graphs.push_back(cm_handle::Graph{std::move(sig), exec, ++h->graph_clock});
+  if ((e = hipGraphLaunch(exec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+cm_status cm_graph_clear(cm_handle* h) {
+  if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
+  DeviceGuard guard(h->device);
+  clear_graphs(h);
   return ok();
 }
 
