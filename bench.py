@@ -177,6 +177,9 @@ def parse():
                     help="only the headline workload (no rate network, no served mix)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served-mix arrival window")
+    ap.add_argument("--serve-queue-seconds", type=float, default=0.0,
+                    help="also serve the mix this long with the conflict-network FP32 requests "
+                         "through the device work queue (0: not run)")
     ap.add_argument("--workload", choices=sorted(SIDE_WORKLOADS), default=None,
                     help="time one other workload of the path instead (prints its own JSON "
                          "line; used to profile each kernel)")
@@ -259,8 +262,10 @@ def rate_network(cm, W):
     return out
 
 
-def serving(cm, seconds):
-    """Served mix: Poisson(50/s) arrivals for `seconds`, continuously batched."""
+def serving(cm, seconds, queue=False):
+    """Served mix: Poisson(50/s) arrivals for `seconds`, continuously batched
+    (with ``queue``: the conflict-network FP32 requests through the device
+    work queue's persistent kernel, the rest through the slots)."""
     import numpy as np
 
     from paper_2110_15425_amd import serve
@@ -268,8 +273,8 @@ def serving(cm, seconds):
     mix = serve.served_mix(n, rate_hz=50.0, seed=11)
     h = cm.Handle(0)
     warm = serve.served_mix(8, rate_hz=1e6, seed=12, max_runs=10_000)
-    serve.run_mix(h, warm)
-    done = serve.run_mix(h, mix, budget_bytes=32 << 30, n_streams=4)
+    serve.run_mix(h, warm, queue=queue)
+    done = serve.run_mix(h, mix, budget_bytes=32 << 30, n_streams=4, queue=queue)
     steps = sum(cm.run_steps(r.w, r.result) for r in done)
     t0 = min(r.arrival for r in done)
     t1 = max(r.done for r in done)
@@ -277,7 +282,7 @@ def serving(cm, seconds):
     summ["by_config"] = serve.latency_by_config(done)
     summ.update({"arrival_rate_hz": 50.0, "window_s": float(mix[-1][0]),
                  "agg_run_steps_per_s": steps / (t1 - t0), "run_steps": int(steps),
-                 "budget_gib": 32, "streams": 4,
+                 "budget_gib": 32, "streams": 4, "device_queue": bool(queue),
                  "mean_runs_per_request": float(np.mean([r.w["n_settings"] * r.w["trials"]
                                                          for r in done]))})
     print(f"# serving: {summ}", file=sys.stderr, flush=True)
@@ -468,6 +473,8 @@ def main():
         line["time_course"] = side_workload("timecourse_c1_fp32", 10, 2)
         line["closed_loop"] = side_workload("loop_l8_m4_fp32", 5, 1)
         line["serving"] = serving(cm, args.serve_seconds)
+        if args.serve_queue_seconds > 0:
+            line["serving_device_queue"] = serving(cm, args.serve_queue_seconds, queue=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w64)
     print(json.dumps(line), flush=True)

@@ -406,6 +406,61 @@ cm_status cm_submit(cm_handle *h, uint32_t n, const cm_model *models, const cm_s
                     void *producer_stream, uint64_t *ticket);
 cm_status cm_poll(cm_handle *h, uint64_t ticket, int *done);
 
+/* Device work queue of the serving path: one persistent simulation kernel
+ * that takes the work of many requests from a queue, so requests that arrive
+ * while others run join the work on the device without a launch of their
+ * own (the continuous batching of evaluations of Sec. 3.6, fed
+ * continuously).  The host publishes each request as a ring entry and a
+ * descriptor in pinned host memory the queue allocates at creation; one
+ * workgroup at a time copies new entries into device memory, and workgroups
+ * claim the requests' items with a fetch-and-add on a device counter.  A
+ * request's items are its preparation pieces (output zero-fill and tables,
+ * as cm_launch's preparation kernel computes them) followed by its chunks,
+ * each run as one workgroup of cm_launch's kernel would run it once the
+ * pieces are done; the workgroup that finishes the last chunk scores the
+ * sweep (when it is scored) and marks the request done in host memory.
+ * Results equal cm_launch's for the same sweep with a 256-thread workgroup;
+ * a request's outputs are complete once cm_queue_poll reports it done.
+ *  cm_queue_create  kind CM_CONFLICT_LCA, precision CM_FP64 or
+ *                   CM_FP32_STEP (else CM_E_UNSUPPORTED); slots: requests
+ *                   in flight (1..4096); groups_per_cu: persistent
+ *                   workgroups per compute unit (1..4; the rest of the GPU
+ *                   stays free for other streams' kernels); idle_us: the
+ *                   kernel ends after this long without an item (100 us ..
+ *                   10 s) and is launched again by the next submit or poll.
+ *                   Allocates the queue's pinned host memory, a small
+ *                   device block (counters and copies of the ring and the
+ *                   descriptors) and two streams of its own, for the kernel
+ *                   and for the host copies (default priority).
+ *  cm_queue_submit  validates like cm_launch, waits until the work enqueued
+ *                   so far on producer_stream is finished (NULL: no
+ *                   producer; the uploads of the sweep's inputs go there),
+ *                   then publishes the request and returns a ticket.  host
+ *                   (or NULL): pinned host buffers (hipHostMalloc; others
+ *                   give CM_E_INVALID) that receive copies of hist, stats,
+ *                   score and best (NULL fields skipped, sizes as in
+ *                   cm_result), enqueued on the queue's copy stream by the
+ *                   first cm_queue_poll that finds the request done on the
+ *                   device.
+ *                   CM_E_BUSY when no slot is free, or when max(512,
+ *                   4 slots) requests have been published since the oldest
+ *                   unfinished one (nothing is published then).  The
+ *                   buffers must stay allocated until the ticket is done.
+ *  cm_queue_poll    *done = 1 once the request's outputs (and, for a scored
+ *                   sweep, its scores) are complete, and its host copies
+ *                   with them; the ticket is then retired.  It never waits.
+ *                   CM_E_INVALID for an unknown ticket.
+ *  cm_queue_destroy asks the kernel to stop, waits for it and frees the
+ *                   queue; unfinished requests are abandoned. */
+typedef struct cm_queue cm_queue;
+cm_status cm_queue_create(cm_handle *h, uint32_t kind, uint32_t precision, uint32_t slots,
+                          uint32_t groups_per_cu, uint32_t idle_us, cm_queue **out);
+cm_status cm_queue_submit(cm_queue *q, const cm_model *model, const cm_sweep *sweep,
+                          const cm_result *result, void *workspace, uint64_t workspace_bytes,
+                          const cm_host_result *host, void *producer_stream, uint64_t *ticket);
+cm_status cm_queue_poll(cm_queue *q, uint64_t ticket, int *done);
+cm_status cm_queue_destroy(cm_queue *q);
+
 /* Measured ceiling of the lane kernels' step: `lanes` lanes (a multiple of
  * 256) each run `steps` steps of the model's random numbers (one Philox
  * block per step, per two steps for the DDM, and its Box-Muller pair) and

@@ -26,7 +26,8 @@ ST = dict(dec0=0, dec1=1, undec=2, correct=3, sumn0=4, sumn1=5, sumsq0=6, sumsq1
 # every symbol include/cm.h declares
 EXPORTS = ["cm_validate", "cm_workspace_bytes", "cm_create", "cm_destroy", "cm_set_tuning",
            "cm_get_tuning", "cm_launch", "cm_launch_scratch", "cm_launch_batch", "cm_launch_graph",
-           "cm_graph_clear", "cm_launch_timecourse",
+           "cm_graph_clear", "cm_queue_create", "cm_queue_submit", "cm_queue_poll",
+           "cm_queue_destroy", "cm_launch_timecourse",
            "cm_unfused_workspace_bytes",
            "cm_launch_unfused", "cm_ddm_density", "cm_serve_config", "cm_submit", "cm_poll",
            "cm_ceiling",
@@ -97,6 +98,13 @@ def lib():
                                       C.POINTER(Result), C.POINTER(C.c_void_p),
                                       C.POINTER(C.c_uint64), C.c_void_p]
         L.cm_graph_clear.argtypes = [C.c_void_p]
+        L.cm_queue_create.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                      C.c_uint32, C.POINTER(C.c_void_p)]
+        L.cm_queue_submit.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep), C.POINTER(Result),
+                                      C.c_void_p, C.c_uint64, C.POINTER(HostResult), C.c_void_p,
+                                      C.POINTER(C.c_uint64)]
+        L.cm_queue_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
+        L.cm_queue_destroy.argtypes = [C.c_void_p]
         L.cm_launch_timecourse.argtypes = [C.c_void_p, C.POINTER(Model), C.POINTER(Sweep),
                                            C.POINTER(Result), C.c_uint32, C.c_void_p, C.c_void_p,
                                            C.c_uint64, C.c_void_p]
@@ -333,6 +341,51 @@ def launch_graph(handle, sweeps, stream=None):
 def graph_clear(handle):
     """Drop every graph the handle keeps (cm_graph_clear)."""
     check(lib().cm_graph_clear(handle.h))
+
+
+class DeviceQueue:
+    """The device work queue (cm_queue_*): one persistent kernel of one kind
+    and precision fed with DeviceSweeps from the host."""
+
+    def __init__(self, handle, kind, precision, slots=64, groups_per_cu=2, idle_us=20000):
+        self.handle = handle
+        q = C.c_void_p(0)
+        check(lib().cm_queue_create(handle.h, int(kind), int(precision), int(slots),
+                                    int(groups_per_cu), int(idle_us), C.byref(q)))
+        self.q = q
+
+    def submit(self, d, stream=None, host=None):
+        """Queue a DeviceSweep after the work on ``stream`` (default: the
+        current torch stream); returns its ticket.  ``host``: a dict of
+        pinned tensors (see host_buffers) that the kernel fills with the
+        results before it marks the request done."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.handle.device)
+        hr = None
+        if host is not None:
+            ptr = lambda k: host[k].data_ptr() if k in host else None  # noqa: E731
+            hr = C.byref(HostResult(ptr("hist"), ptr("stats"), ptr("score"), ptr("best")))
+        t = C.c_uint64(0)
+        check(lib().cm_queue_submit(self.q, C.byref(d.model), C.byref(d.sweep), C.byref(d.result),
+                                    C.c_void_p(d.workspace.data_ptr()), d.workspace.numel(), hr,
+                                    C.c_void_p(st.cuda_stream), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        done = C.c_int(0)
+        check(lib().cm_queue_poll(self.q, int(ticket), C.byref(done)))
+        return bool(done.value)
+
+    def close(self):
+        if self.q:
+            check(lib().cm_queue_destroy(self.q))
+            self.q = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def serve_config(handle, n_slots):

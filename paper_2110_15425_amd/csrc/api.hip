@@ -54,6 +54,47 @@ static void clear_graphs(cm_handle* h) {
   h->graphs.clear();
 }
 
+// The device work queue: pinned host memory the host publishes into
+// (header, done words, item ring, request descriptors), device counters the
+// persistent kernel claims and counts with, and the host's view of the
+// requests in flight.
+struct cm_queue {
+  cm_handle* h = nullptr;
+  uint32_t kind = 0, prec = 0, cap_slots = 0, cap_ring = 0, groups = 0;
+  uint64_t idle_ticks = 0;
+  size_t lds = 0;
+  char* host = nullptr;  // pinned: [tail, stop, pad...][done][ring][desc]
+  uint32_t* tail = nullptr;
+  uint32_t* stop = nullptr;
+  uint32_t* done = nullptr;
+  cm::QueueReq* ring = nullptr;
+  cm::QueueDesc* desc = nullptr;
+  char* dev = nullptr;  // device: claim word, dev_tail, pull_lock, dev_stop, prep_done[cap_slots],
+                        // chunk_done[cap_slots], then the ring and descriptor copies
+  size_t o_dring = 0, o_ddesc = 0;
+  hipStream_t run = nullptr;
+  hipEvent_t run_done = nullptr;
+  bool launched = false;
+  uint32_t published = 0;  // requests published (== *tail)
+  uint64_t next_ticket = 1;
+  std::vector<uint64_t> slot_prep, slot_chunks;  // pieces and chunks ever assigned to each slot
+  std::vector<uint64_t> slot_ticket;  // 0: free
+  hipStream_t copy = nullptr;            // result copies into host buffers
+  std::vector<hipEvent_t> copied;        // per slot: the copies of its request are finished
+  struct Copy {
+    void* dst;
+    const void* src;
+    uint64_t bytes;
+  };
+  struct Req {
+    uint64_t ticket;
+    uint32_t slot, number;  // number: publication order
+    bool copying;           // the device is done; the host copies are enqueued
+    Copy cp[4];             // hist, stats, score, best (dst NULL: none)
+  };
+  std::vector<Req> reqs;  // in publication order
+};
+
 // Workspace of cm_launch_scratch: one array per device, living as long as
 // the process.  In host code `scratch` names a host-side stand-in, not the
 // device array: its device address comes from hipGetSymbolAddress (taken once
@@ -396,10 +437,10 @@ uint32_t lane_block(const cm_tuning& t, bool timecourse) { return timecourse ? 2
 
 cm_status plan_lane(cm_handle* h, const cm_model* m, const cm_sweep* s, const cm_result* r, char* ws,
                     const Layout& L, uint32_t scan_block, uint64_t launch_runs, const TcSpec& tc,
-                    cm::SimArgs& a, uint64_t& groups, size_t& lds) {
+                    cm::SimArgs& a, uint64_t& groups, size_t& lds, uint32_t force_block = 0) {
   const bool scan = scan_block != 0;
   const cm_tuning& tune = h->tune[m->kind][m->precision];
-  const uint32_t block = lane_block(tune, tc.every != 0);
+  const uint32_t block = force_block ? force_block : lane_block(tune, tc.every != 0);
   const double* p = m->params;
   const uint64_t S = s->n_settings, T = s->trials, runs = S * T;
   const uint32_t B = s->n_bins;
@@ -1216,6 +1257,260 @@ cm_status cm_graph_clear(cm_handle* h) {
   if (!h) return fail(CM_E_INVALID, "handle must not be NULL");
   DeviceGuard guard(h->device);
   clear_graphs(h);
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Launch the queue's persistent kernel unless it is still running (it ends
+// by itself after idle_ticks without an item).
+cm_status queue_ensure_running(cm_queue* q) {
+  if (q->launched) {
+    const hipError_t e = hipEventQuery(q->run_done);
+    if (e == hipErrorNotReady) return ok();
+    if (e != hipSuccess) return hip_fail(e, "queue kernel");
+  }
+  cm::QueueArgs a{};
+  a.tail = q->tail;
+  a.stop = q->stop;
+  a.done = q->done;
+  a.ring = q->ring;
+  a.desc = q->desc;
+  a.cap_ring = q->cap_ring;
+  a.word = (unsigned long long*)q->dev;
+  a.dev_tail = (uint32_t*)(q->dev + 64);
+  a.pull_lock = (uint32_t*)(q->dev + 128);
+  a.dev_stop = (uint32_t*)(q->dev + 192);
+  a.prep_done = (unsigned long long*)(q->dev + 256);
+  a.chunk_done = a.prep_done + q->cap_slots;
+  a.dring = (cm::QueueReq*)(q->dev + q->o_dring);
+  a.ddesc = (cm::QueueDesc*)(q->dev + q->o_ddesc);
+  a.idle_ticks = q->idle_ticks;
+  hipError_t e;
+  if ((e = cm::launch_queue((int)q->kind, (int)q->prec, a, q->groups, q->lds, q->run)) != hipSuccess)
+    return hip_fail(e, "queue kernel");
+  if ((e = hipEventRecord(q->run_done, q->run)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  q->launched = true;
+  return ok();
+}
+
+void queue_free(cm_queue* q) {
+  if (q->run) {
+    if (q->stop) __atomic_store_n(q->stop, 1u, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(q->run);
+    (void)hipStreamDestroy(q->run);
+  }
+  if (q->run_done) (void)hipEventDestroy(q->run_done);
+  if (q->copy) {
+    (void)hipStreamSynchronize(q->copy);
+    (void)hipStreamDestroy(q->copy);
+  }
+  for (hipEvent_t ev : q->copied) (void)hipEventDestroy(ev);
+  if (q->host) (void)hipHostFree(q->host);
+  if (q->dev) (void)hipFree(q->dev);
+  delete q;
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_queue_create(cm_handle* h, uint32_t kind, uint32_t precision, uint32_t slots, uint32_t groups_per_cu,
+                          uint32_t idle_us, cm_queue** out) {
+  if (!h || !out) return fail(CM_E_INVALID, "handle and out must not be NULL");
+  *out = nullptr;
+  if (kind != CM_CONFLICT_LCA || (precision != CM_FP64 && precision != CM_FP32_STEP))
+    return fail(CM_E_UNSUPPORTED, "the device queue runs conflict-LCA sweeps in FP64 or FP32 steps");
+  if (slots < 1 || slots > 4096) return fail(CM_E_INVALID, "slots in [1, 4096]");
+  if (groups_per_cu < 1 || groups_per_cu > 4) return fail(CM_E_INVALID, "groups_per_cu in [1, 4]");
+  if (idle_us < 100 || idle_us > 10000000) return fail(CM_E_INVALID, "idle_us in [100, 10^7]");
+  DeviceGuard guard(h->device);
+  cm_queue* q = new (std::nothrow) cm_queue();
+  if (!q) return fail(CM_E_DEVICE, "out of host memory");
+  q->h = h;
+  q->kind = kind;
+  q->prec = precision;
+  q->cap_slots = slots;
+  q->cap_ring = std::max<uint32_t>(512u, 4u * slots);  // requests between the oldest unfinished one and the newest
+  q->groups = groups_per_cu * (uint32_t)h->cu_count;
+  q->idle_ticks = (uint64_t)idle_us * 100u;  // the real-time clock runs at 100 MHz
+  q->lds = cm::lane_stage_bytes((int)kind, (int)precision, 256) + kLdsBudget;
+  if (q->lds > h->lds_per_block) {
+    delete q;
+    return fail(CM_E_UNSUPPORTED, "queue kernel: LDS too small on this device");
+  }
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t o_done = 256, o_ring = up(o_done + 4u * (size_t)slots),
+               o_desc = up(o_ring + sizeof(cm::QueueReq) * (size_t)q->cap_ring),
+               bytes = o_desc + sizeof(cm::QueueDesc) * (size_t)slots;
+  hipError_t e;
+  if ((e = hipHostMalloc((void**)&q->host, bytes, hipHostMallocCoherent)) != hipSuccess) {
+    delete q;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  memset(q->host, 0, bytes);
+  q->tail = (uint32_t*)q->host;
+  q->stop = (uint32_t*)(q->host + 64);
+  q->done = (uint32_t*)(q->host + o_done);
+  q->ring = (cm::QueueReq*)(q->host + o_ring);
+  q->desc = (cm::QueueDesc*)(q->host + o_desc);
+  q->o_dring = up(256 + 16u * (size_t)slots);
+  q->o_ddesc = up(q->o_dring + sizeof(cm::QueueReq) * (size_t)q->cap_ring);
+  const size_t dbytes = q->o_ddesc + sizeof(cm::QueueDesc) * (size_t)slots;
+  if ((e = hipMalloc((void**)&q->dev, dbytes)) != hipSuccess || (e = hipMemset(q->dev, 0, dbytes)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&q->run, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&q->run_done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&q->copy, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    queue_free(q);
+    return hip_fail(e, "queue set-up");
+  }
+  q->copied.assign(slots, nullptr);
+  for (uint32_t i = 0; i < slots; ++i)
+    if ((e = hipEventCreateWithFlags(&q->copied[i], hipEventDisableTiming)) != hipSuccess) {
+      queue_free(q);
+      return hip_fail(e, "queue set-up");
+    }
+  q->slot_prep.assign(slots, 0);
+  q->slot_chunks.assign(slots, 0);
+  q->slot_ticket.assign(slots, 0);
+  *out = q;
+  return ok();
+}
+
+cm_status cm_queue_submit(cm_queue* q, const cm_model* m, const cm_sweep* s, const cm_result* r, void* workspace,
+                          uint64_t workspace_bytes, const cm_host_result* host, void* producer_stream,
+                          uint64_t* ticket) {
+  if (!q || !ticket) return fail(CM_E_INVALID, "queue and ticket must not be NULL");
+  Layout L;
+  cm_status st = check_launch(m, s, r, workspace, workspace_bytes, L);
+  if (st != CM_OK) return st;
+  if (m->kind != q->kind || m->precision != q->prec)
+    return fail(CM_E_UNSUPPORTED, "the queue runs one kind and precision");
+  cm_handle* h = q->h;
+  DeviceGuard guard(h->device);
+  cm::SimArgs a;
+  uint64_t groups = 0;
+  size_t lds = 0;
+  if ((st = plan_lane(h, m, s, r, (char*)workspace, L, 0, s->n_settings * s->trials, TcSpec{}, a, groups, lds,
+                      256)) != CM_OK)
+    return st;
+  if (lds > q->lds) return fail(CM_E_UNSUPPORTED, "request needs more LDS than the queue kernel has");
+  cm::PrepBatch pb{};
+  fill_prep(m, s, r, (char*)workspace, L, pb);
+  cm::ScoreBatch sb{};
+  fill_score(m, s, r, sb);
+  const uint64_t pieces = (pb.it[0].end + cm::kQueuePrepSpan - 1) / cm::kQueuePrepSpan;
+  const uint64_t n_items = pieces + groups;
+  if (n_items >= 0xFFFFFFFFull) return fail(CM_E_UNSUPPORTED, "the sweep is too large for the queue");
+  if (q->published == 0xFFFFFFFFu) return fail(CM_E_UNSUPPORTED, "the queue has published 2^32 - 1 requests");
+  // room: a free slot, and ring space behind the oldest unfinished request
+  uint32_t slot = q->cap_slots;
+  for (uint32_t i = 0; i < q->cap_slots; ++i)
+    if (!q->slot_ticket[i]) {
+      slot = i;
+      break;
+    }
+  const uint32_t oldest = q->reqs.empty() ? q->published : q->reqs.front().number;
+  if (slot == q->cap_slots || q->published - oldest >= q->cap_ring) return fail(CM_E_BUSY, "queue full");
+  // host copies, enqueued by cm_queue_poll once the device is done: pinned
+  // buffers, so that the copies run asynchronously
+  cm_queue::Copy cp[4] = {};
+  if (host) {
+    const uint64_t S = s->n_settings;
+    const cm_queue::Copy want[4] = {{host->hist, r->hist, S * 2u * s->n_bins * 8u},
+                                    {host->stats, r->stats, S * CM_NSTAT * 8u},
+                                    {host->score, r->score, S * 8u},
+                                    {host->best, r->best, 16u}};
+    for (int i = 0; i < 4; ++i) {
+      if (!want[i].dst || !want[i].src) continue;
+      hipPointerAttribute_t at{};
+      if (hipPointerGetAttributes(&at, want[i].dst) != hipSuccess || at.type != hipMemoryTypeHost) {
+        (void)hipGetLastError();
+        return fail(CM_E_INVALID, "host result buffers must be pinned host memory (hipHostMalloc)");
+      }
+      cp[i] = want[i];
+    }
+  }
+  // the producer's work on the buffers (their uploads) is finished before any
+  // item can run
+  hipError_t e;
+  if (producer_stream) {
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventRecord(ev, (hipStream_t)producer_stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "producer hand-off");
+  }
+  const uint64_t t = q->next_ticket++;
+  cm::QueueDesc& d = q->desc[slot];
+  d.a = a;
+  d.prep = pb.it[0];
+  d.score = sb.n ? sb.a[0] : cm::ScoreArgs{};
+  d.scored = sb.n ? 1u : 0u;
+  d.prep_target = q->slot_prep[slot] + pieces;
+  d.chunk_target = q->slot_chunks[slot] + groups;
+  d.pieces = (uint32_t)pieces;
+  d.ticket = (uint32_t)t;
+  d.pad = 0;
+  cm::QueueReq& ent = q->ring[q->published % q->cap_ring];
+  ent.num_items = ((unsigned long long)q->published << 32) | n_items;
+  ent.slot = slot;
+  ent.pad = 0;
+  q->slot_prep[slot] += pieces;
+  q->slot_chunks[slot] += groups;
+  q->slot_ticket[slot] = t;
+  q->reqs.push_back(cm_queue::Req{t, slot, q->published, false, {cp[0], cp[1], cp[2], cp[3]}});
+  q->published += 1u;
+  __atomic_store_n(q->tail, q->published, __ATOMIC_RELEASE);  // publish after the entry and descriptor
+  *ticket = t;
+  return queue_ensure_running(q);
+}
+
+cm_status cm_queue_poll(cm_queue* q, uint64_t ticket, int* done) {
+  if (!q || !done) return fail(CM_E_INVALID, "queue and done must not be NULL");
+  *done = 0;
+  size_t k = 0;
+  while (k < q->reqs.size() && q->reqs[k].ticket != ticket) ++k;
+  if (k == q->reqs.size()) return fail(CM_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  DeviceGuard guard(q->h->device);
+  cm_queue::Req& rq = q->reqs[k];
+  hipError_t e;
+  if (!rq.copying) {
+    if (__atomic_load_n(&q->done[rq.slot], __ATOMIC_ACQUIRE) != (uint32_t)ticket)
+      return queue_ensure_running(q);  // relaunch if the kernel went idle before this request's items
+    bool any = false;
+    for (const auto& c : rq.cp) {
+      if (!c.dst) continue;
+      if ((e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost, q->copy)) != hipSuccess)
+        return hip_fail(e, "result copy");
+      any = true;
+    }
+    rq.copying = true;
+    if (any && (e = hipEventRecord(q->copied[rq.slot], q->copy)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (!any) {
+      q->slot_ticket[rq.slot] = 0;
+      q->reqs.erase(q->reqs.begin() + (ptrdiff_t)k);
+      *done = 1;
+      return ok();
+    }
+  }
+  e = hipEventQuery(q->copied[rq.slot]);
+  if (e == hipErrorNotReady) return ok();
+  if (e != hipSuccess) return hip_fail(e, "result copy");
+  q->slot_ticket[rq.slot] = 0;
+  q->reqs.erase(q->reqs.begin() + (ptrdiff_t)k);
+  *done = 1;
+  return ok();
+}
+
+cm_status cm_queue_destroy(cm_queue* q) {
+  if (!q) return ok();
+  DeviceGuard guard(q->h->device);
+  queue_free(q);
   return ok();
 }
 

@@ -118,6 +118,56 @@ struct ScoreBatch {
   ScoreArgs a[kMaxBatch];
 };
 
+// Device work queue of the serving path: a persistent lane kernel takes
+// requests that the host publishes in pinned host memory, each as (slot,
+// item count) in a ring and a descriptor per slot.  A request's items are its
+// preparation pieces (zero-fill and tables) and then its chunks, each run as
+// one workgroup of the batched kernel would run it; the chunks wait for the
+// preparation, and the workgroup that finishes the last chunk scores the
+// sweep (when it is scored) and marks the request done.  One workgroup at a
+// time copies newly published ring entries and their descriptors into
+// device memory, so host memory is read once per request.  Workgroups claim
+// items with one fetch-and-add on a 64-bit word holding (request index, next
+// item); the word moves to the next request by compare-and-swap only once
+// every item of the current one is claimed.
+constexpr uint64_t kQueuePrepSpan = 1u << 16;  // preparation indices per piece
+struct QueueReq {
+  // (publication number << 32) | item count, read and written as one word:
+  // the number tells a stale entry from the one that replaced it
+  unsigned long long num_items;
+  uint32_t slot, pad;
+};
+struct QueueDesc {
+  SimArgs a;
+  PrepItem prep;
+  ScoreArgs score;
+  uint64_t prep_target;   // the slot's preparation pieces once this request's are done
+  uint64_t chunk_target;  // the slot's chunks once this request's are done
+  uint32_t pieces;        // items [0, pieces) are preparation pieces, the rest chunks
+  uint32_t ticket;        // low 32 bits of the request's ticket, stored in done[slot] at the end
+  uint32_t scored;
+  uint32_t pad;
+};
+static_assert(sizeof(QueueDesc) % 8 == 0, "descriptors are copied in 8-byte words");
+struct QueueArgs {
+  const uint32_t* tail;   // HOST: requests published so far
+  const uint32_t* stop;   // HOST: non-zero ends the kernel
+  uint32_t* done;         // HOST [slots]: ticket of the slot's last finished request
+  const QueueReq* ring;   // HOST [cap_ring]: request i at i % cap_ring
+  const QueueDesc* desc;  // HOST [slots]
+  uint32_t cap_ring;
+  uint32_t pad;
+  unsigned long long* word;  // DEVICE: (request index << 32) | next item of that request
+  uint32_t* dev_tail;        // DEVICE: requests copied to the device so far (<= *tail)
+  uint32_t* pull_lock;       // DEVICE: 1 while one workgroup reads the host's queue
+  uint32_t* dev_stop;        // DEVICE: the host's stop flag, as last read
+  QueueReq* dring;           // DEVICE [cap_ring]: copies of the host's ring
+  QueueDesc* ddesc;          // DEVICE [slots]: copies of the host's descriptors
+  unsigned long long* prep_done;   // DEVICE [slots]: preparation pieces finished, cumulative
+  unsigned long long* chunk_done;  // DEVICE [slots]: chunks finished, cumulative
+  uint64_t idle_ticks;             // real-time clock ticks without an item before exiting
+};
+
 // Arguments of the rate-network kernels.
 struct RnnArgs {
   uint64_t trials, n_settings, total_runs, seed;
@@ -197,6 +247,10 @@ hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc
 hipError_t launch_prep(const PrepBatch& b, hipStream_t st);
 hipError_t launch_ceiling(int kind, int precision, const SimArgs& a, uint32_t steps, uint64_t lanes,
                           double* out, hipStream_t st);
+// The persistent queue kernel of kind/precision (conflict LCA) on `groups`
+// workgroups of 256 threads with lds_bytes of dynamic LDS.
+hipError_t launch_queue(int kind, int precision, const QueueArgs& q, uint32_t groups, size_t lds_bytes,
+                        hipStream_t st);
 // LDS after the histogram window (and the time-course blocks) that the lane
 // kernel uses to pack unfinished runs while a chunk drains.
 size_t lane_stage_bytes(int kind, int precision, uint32_t block);

@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "internal.hpp"
+#include "prep_score.hpp"
 #include "lca_step.hpp"
 #include "rng.hpp"
 
@@ -545,16 +546,13 @@ struct LCA : std::conditional<PREC == CM_FP64, LcaDrive64, LcaDrive32>::type {
 // registers so that that many wavefronts fit on each SIMD (the register use
 // versus occupancy trade-off of the paper's GPU study, Sec. 6.3; a cap below
 // the kernel's natural use spills or recomputes values).
-template <class M, bool TC, int OCC, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1)))
-void sim_lane_kernel(LaneBatch batch) {
-  extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
-  uint32_t* lds = (uint32_t*)lds_u64;
-  __shared__ uint32_t next;
-  uint32_t sw = 0;
-  while (sw + 1 < batch.n && blockIdx.x >= batch.base[sw + 1]) ++sw;
-  const SimArgs& a = batch.a[sw];
-  const uint64_t r0 = (uint64_t)(blockIdx.x - batch.base[sw]) * a.chunk;
+// One workgroup's chunk of a sweep: runs r0 .. r0 + chunk - 1 through the
+// refill queue, the drain and the window flush.  lds: the dynamic LDS (the
+// window, then the drain stage); next, drain_cnt: the workgroup's own
+// counters.
+template <class M, bool TC, int BLOCK>
+__device__ __forceinline__ void lane_chunk(const SimArgs& a, uint64_t r0, uint32_t* lds, uint32_t& next,
+                                           uint32_t* drain_cnt) {
   const uint64_t r1 = min(r0 + a.chunk, a.total_runs);
   const uint32_t len = (uint32_t)(r1 - r0);
   const uint32_t s_lo = (uint32_t)(r0 / a.trials);
@@ -583,7 +581,6 @@ void sim_lane_kernel(LaneBatch batch) {
   Lane L;
   uint32_t off = threadIdx.x;
   bool have = off < len;
-  __shared__ uint32_t drain_cnt[BLOCK / 64];
   auto setup = [&](uint32_t o) {
     const uint32_t local = t_lo + o;  // < 2^31 + chunk
     L.s = s_lo + udiv_magic(local, a.trials_magic);
@@ -665,6 +662,207 @@ void sim_lane_kernel(LaneBatch batch) {
     }
   }
   if (!a.direct) flush(a, lds, s_lo);  // the last barrier follows every record
+}
+
+template <class M, bool TC, int OCC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : 1)))
+void sim_lane_kernel(LaneBatch batch) {
+  extern __shared__ unsigned long long lds_u64[];  // 8-byte aligned window
+  __shared__ uint32_t next;
+  __shared__ uint32_t drain_cnt[BLOCK / 64];
+  uint32_t sw = 0;
+  while (sw + 1 < batch.n && blockIdx.x >= batch.base[sw + 1]) ++sw;
+  const SimArgs& a = batch.a[sw];
+  lane_chunk<M, TC, BLOCK>(a, (uint64_t)(blockIdx.x - batch.base[sw]) * a.chunk, (uint32_t*)lds_u64, next,
+                           drain_cnt);
+}
+
+// The persistent kernel of the device work queue.
+//
+// Claim: thread 0 reads the claim word (r, c) and the device's copy count.
+// While request r is copied to the device and has items left (c below its
+// count), one fetch-and-add takes the next item -- whichever request the
+// word names by then, which is at most the newest copied one, so the item is
+// run if it exists.  Once every item of r is claimed and r + 1 is copied, a
+// compare-and-swap moves the word to (r + 1, 0); increments that raced past
+// the count are dropped with it.  With nothing to claim, the one workgroup
+// that takes the pull lock reads the host's count and copies newly published
+// ring entries and their descriptors into device memory (batch by batch,
+// moving the copy count forward), or passes on the host's stop flag.  A
+// workgroup ends when the stop flag is set or when nothing came for
+// idle_ticks of the real-time clock.  Waiting loops read with relaxed loads
+// and take one acquire fence once their condition holds, so an idle
+// workgroup does not keep invalidating the caches of the busy ones.
+//
+// A preparation piece zero-fills and writes its share of the request's
+// outputs and tables, then counts itself done (release); a chunk first waits
+// until every piece of its request is done -- a request's pieces are its
+// first items, so they are running or finished -- and then runs as
+// lane_chunk.  The workgroup that finishes a request's last chunk scores the
+// sweep when it is scored and stores the request's ticket in its
+// host-visible done word with a system-scope release.  Before each count or
+// store that publishes work, every wavefront waits until its own stores and
+// atomics are performed, the workgroup meets at a barrier, and thread 0
+// publishes with one release: one L2 write-back per chunk, where a fence in
+// every wavefront would write the L2 back once per wavefront.  A workgroup
+// waits for a request's preparation (acquire) only on its first chunk of it.
+template <class M>
+__global__ __launch_bounds__(kBlock) void queue_kernel(QueueArgs q) {
+  extern __shared__ unsigned long long lds_u64[];
+  __shared__ uint32_t next;
+  __shared__ uint32_t drain_cnt[kBlock / 64];
+  __shared__ QueueDesc desc;
+  __shared__ uint32_t claim[3];  // action, then (slot, item) or the pull's range [from, to)
+  __shared__ QueueReq batch[kBlock];
+  __shared__ double red_d[kBlock / 64];
+  __shared__ unsigned long long red_k[kBlock / 64], red_c[kBlock / 64];
+  constexpr uint32_t kItem = 0, kQuit = 1, kPull = 2;
+  uint32_t seen_slot = ~0u;  // thread 0: the request whose preparation this workgroup last waited for
+  uint64_t seen_target = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t action = kQuit, w1 = 0, w2 = 0;
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      for (;;) {
+        const unsigned long long w = __hip_atomic_load(q.word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t r = (uint32_t)(w >> 32), c = (uint32_t)w;
+        const uint32_t dt = __hip_atomic_load(q.dev_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (r < dt) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the copies made before dev_tail passed r
+          // An entry whose number is not r was replaced by a later request,
+          // which the host publishes only once r is done: r has no items left.
+          const unsigned long long ni =
+              __hip_atomic_load(&q.dring[r % q.cap_ring].num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((uint32_t)(ni >> 32) == r && c < (uint32_t)ni) {
+            const unsigned long long v = __hip_atomic_fetch_add(q.word, 1ull, __ATOMIC_ACQUIRE,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t r2 = (uint32_t)(v >> 32), c2 = (uint32_t)v;
+            const QueueReq* e2 = q.dring + r2 % q.cap_ring;
+            const unsigned long long ni2 = __hip_atomic_load(&e2->num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(ni2 >> 32) == r2 && c2 < (uint32_t)ni2) {  // a held item keeps r2's entry in place
+              action = kItem;
+              w1 = __hip_atomic_load(&e2->slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              w2 = c2;
+              break;
+            }
+            continue;  // raced past the last item of r2
+          }
+          if (r + 1u < dt) {  // every item of r is claimed and r + 1 is on the device
+            unsigned long long expect = w;
+            __hip_atomic_compare_exchange_strong(q.word, &expect, (unsigned long long)(r + 1u) << 32,
+                                                 __ATOMIC_RELEASE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+          }
+        }
+        if (__hip_atomic_load(q.pull_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+            atomicCAS(q.pull_lock, 0u, 1u) == 0u) {
+          const uint32_t ht = __hip_atomic_load(q.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          // a read-modify-write returns the latest copy count, with no fence
+          const uint32_t d2 = __hip_atomic_fetch_add(q.dev_tail, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ht != d2) {  // the lock is held until the copy is published
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // system scope: the host's ring and descriptors
+            action = kPull;
+            w1 = d2;
+            w2 = ht;
+            break;
+          }
+          if (__hip_atomic_load(q.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+            __hip_atomic_store(q.dev_stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // nothing was written under the lock: a plain release of it (a
+          // release fence here, in every idle workgroup's loop, would write
+          // back the L2 under the busy workgroups again and again)
+          __hip_atomic_store(q.pull_lock, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (__hip_atomic_load(q.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            __builtin_amdgcn_s_memrealtime() - t0 > q.idle_ticks)
+          break;  // kQuit
+        __builtin_amdgcn_s_sleep(64);
+      }
+      claim[0] = action;
+      claim[1] = w1;
+      claim[2] = w2;
+    }
+    __syncthreads();
+    const uint32_t action = claim[0];
+    if (action == kQuit) return;  // the whole workgroup; it holds no lock
+    if (action == kPull) {
+      const uint32_t from = claim[1], to = claim[2];
+      for (uint32_t base = from; base != to;) {  // counts wrap only past 2^32 requests, which the host refuses
+        const uint32_t n = min(to - base, (uint32_t)kBlock);
+        if (threadIdx.x < n) {
+          const uint32_t at = (base + threadIdx.x) % q.cap_ring;
+          QueueReq e;
+          e.num_items = __hip_atomic_load(&q.ring[at].num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          e.slot = __hip_atomic_load(&q.ring[at].slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          e.pad = 0;
+          batch[threadIdx.x] = e;
+          __hip_atomic_store(&q.dring[at].slot, e.slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&q.dring[at].num_items, e.num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < n; ++k) {  // every entry starts a request: copy its descriptor
+          const unsigned long long* src = (const unsigned long long*)&q.desc[batch[k].slot];
+          unsigned long long* dst = (unsigned long long*)&q.ddesc[batch[k].slot];
+          for (uint32_t i = threadIdx.x; i < sizeof(QueueDesc) / 8u; i += kBlock)
+            dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        base += n;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies are stored
+        __syncthreads();                // and every wave's; batch[] is free
+        if (threadIdx.x == 0) __hip_atomic_store(q.dev_tail, base, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (threadIdx.x == 0) __hip_atomic_store(q.pull_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t slot = claim[1], item = claim[2];
+    {
+      const unsigned long long* src = (const unsigned long long*)&q.ddesc[slot];
+      unsigned long long* dst = (unsigned long long*)&desc;
+      for (uint32_t i = threadIdx.x; i < sizeof(QueueDesc) / 8u; i += kBlock)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (item < desc.pieces) {
+      const uint64_t j0 = (uint64_t)item * kQueuePrepSpan;
+      const uint64_t j1 = min(j0 + kQueuePrepSpan, desc.prep.end);
+      for (uint64_t j = j0 + threadIdx.x; j < j1; j += kBlock) prep_index(desc.prep, j);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&q.prep_done[slot], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      continue;
+    }
+    if (threadIdx.x == 0 && (slot != seen_slot || desc.prep_target != seen_target)) {
+      while (__hip_atomic_load(&q.prep_done[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < desc.prep_target)
+        __builtin_amdgcn_s_sleep(16);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      seen_slot = slot;  // this request's tables are visible to the workgroup from now on
+      seen_target = desc.prep_target;
+    }
+    __syncthreads();
+    lane_chunk<M, false, kBlock>(desc.a, (uint64_t)(item - desc.pieces) * desc.a.chunk, (uint32_t*)lds_u64,
+                                 next, drain_cnt);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's flushes are performed
+    __syncthreads();                // and every wave's
+    if (threadIdx.x == 0) {
+      const uint64_t old = __hip_atomic_fetch_add(&q.chunk_done[slot], 1ull, __ATOMIC_RELEASE,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      const bool last = old + 1ull == desc.chunk_target;
+      if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every chunk's flushes
+      claim[2] = last;
+    }
+    __syncthreads();
+    if (claim[2]) {  // the request's last chunk
+      if (desc.scored) score_sweep<kBlock / 64>(desc.score, red_d, red_k, red_c);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&q.done[slot], desc.ticket, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();  // claim[], desc and the LDS are free for the next item
+  }
 }
 
 // Drift-diffusion with one wavefront per run.  Each lane draws one random
@@ -848,6 +1046,16 @@ hipError_t launch_sim_lane(int kind, int precision, uint32_t scan_block, bool tc
                                 : launch_model<DDM<CM_FP32_STEP>>(b, tc, occ, block, lds_bytes, st);
   return precision == CM_FP64 ? launch_model<LCA<CM_FP64>>(b, tc, occ, block, lds_bytes, st)
                               : launch_model<LCA<CM_FP32_STEP>>(b, tc, occ, block, lds_bytes, st);
+}
+
+hipError_t launch_queue(int kind, int precision, const QueueArgs& q, uint32_t groups, size_t lds_bytes,
+                        hipStream_t st) {
+  if (kind != CM_CONFLICT_LCA || groups < 1) return hipErrorInvalidValue;
+  if (precision == CM_FP64)
+    hipLaunchKernelGGL(queue_kernel<LCA<CM_FP64>>, dim3(groups), dim3(kBlock), lds_bytes, st, q);
+  else
+    hipLaunchKernelGGL(queue_kernel<LCA<CM_FP32_STEP>>, dim3(groups), dim3(kBlock), lds_bytes, st, q);
+  return hipGetLastError();
 }
 
 size_t lane_stage_bytes(int kind, int precision, uint32_t block) {

@@ -158,6 +158,65 @@ class GpuBackend:
         return out
 
 
+class QueueBackend(GpuBackend):
+    """GpuBackend with the device work queue in front: requests of the
+    queue's kind and precision (conflict-network sweeps in FP32 steps) join
+    the work of one persistent kernel as they arrive (cm_queue_submit),
+    without a launch of their own; the others go to the serving slots.
+    A request the queue has no room for goes to its slot too."""
+
+    def __init__(self, handle, n_streams=4, dumps=False, queue_slots=256,
+                 groups_per_cu=2, idle_us=2000):
+        super().__init__(handle, n_streams, dumps)
+        self.queue = cm.DeviceQueue(handle, W.LCA, W.FP32_STEP, slots=queue_slots,
+                                    groups_per_cu=groups_per_cu, idle_us=idle_us)
+
+    def close(self):
+        self.queue.close()
+
+    @staticmethod
+    def _queued(w):
+        return int(w["kind"]) == W.LCA and int(w["precision"]) == W.FP32_STEP
+
+    def launch(self, si, ws):
+        queued, rest = [], []
+        for i, w in enumerate(ws):
+            if self._queued(w):
+                d = cm.DeviceSweep(self.h, w, dumps=self.dumps)
+                hh = cm.host_buffers(d)
+                try:
+                    queued.append((i, (d, hh), self.queue.submit(d, host=hh)))
+                    continue
+                except cm.CmError as e:
+                    if e.status != cm.E_BUSY:
+                        raise
+            rest.append(i)
+        slot = super().launch(si, [ws[i] for i in rest]) if rest else None
+        return (queued, rest, slot, len(ws))
+
+    def poll(self, token):
+        queued, rest, slot, n = token
+        for k, (i, d, t) in enumerate(queued):
+            if t is not None and self.queue.poll(t):
+                queued[k] = (i, d, None)  # retired: polled done once
+        if any(t is not None for _, _, t in queued):
+            return None
+        slot_out = None
+        if slot is not None:
+            slot_out = super().poll(slot)
+            if slot_out is None:
+                return None
+        out = [None] * n
+        for i, (d, hh), _ in queued:  # the kernel wrote the results into the pinned buffers
+            o = {k: (t.numpy().view(np.uint64) if k in ("hist", "stats") else t.numpy()) for k, t in hh.items()}
+            if self.dumps:
+                o["device_sweep"] = d
+            out[i] = o
+        for i, o in zip(rest, slot_out or []):
+            out[i] = o
+        return out
+
+
 def served_mix(n_requests, rate_hz=50.0, seed=11, max_runs=10 ** 6, fp32=True):
     """The served-mix workload: Poisson arrivals at rate_hz; each request picks
     one of the four model configurations uniformly, a log-uniform total run
@@ -189,21 +248,28 @@ def served_mix(n_requests, rate_hz=50.0, seed=11, max_runs=10 ** 6, fp32=True):
     return out
 
 
-def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4, dumps=False):
+def run_mix(handle, mix, budget_bytes=32 << 30, n_streams=4, dumps=False, queue=False, queue_opts=None):
     """Replay a served mix in real time; returns the finished requests.  With
     ``dumps`` every request also writes its per-run outcomes, left on the
-    device in ``result["device_sweep"]`` (its ``results()`` reads them)."""
-    be = GpuBackend(handle, n_streams, dumps=dumps)
-    sch = Scheduler(be, budget_bytes, n_streams)
-    t0 = be.clock()
-    pending = collections.deque(Request(i, w, t0 + dt) for i, (dt, w) in enumerate(mix))
-    while pending or not sch.idle():
-        now = be.clock()
-        while pending and pending[0].arrival <= now:
-            sch.submit(pending.popleft())
-        sch.tick()
-        time.sleep(0.0002)
-    return sch.finished
+    device in ``result["device_sweep"]`` (its ``results()`` reads them).
+    With ``queue`` the conflict-network FP32 requests go through the device
+    work queue (QueueBackend, given ``queue_opts`` as keyword arguments)."""
+    be = (QueueBackend(handle, n_streams, dumps=dumps, **(queue_opts or {})) if queue
+          else GpuBackend(handle, n_streams, dumps=dumps))
+    try:
+        sch = Scheduler(be, budget_bytes, n_streams)
+        t0 = be.clock()
+        pending = collections.deque(Request(i, w, t0 + dt) for i, (dt, w) in enumerate(mix))
+        while pending or not sch.idle():
+            now = be.clock()
+            while pending and pending[0].arrival <= now:
+                sch.submit(pending.popleft())
+            sch.tick()
+            time.sleep(0.0002)
+        return sch.finished
+    finally:
+        if queue:
+            be.close()
 
 
 CONFIG_NAMES = {0: "ddm", 1: "conflict", 2: "grid_search", 3: "rate_network"}

@@ -24,6 +24,23 @@ def test_mix_equals_alone():
     assert lat["p99_ms"] >= lat["p50_ms"] > 0
 
 
+def test_mix_through_the_device_queue_equals_alone():
+    """The same served mix with the conflict-network FP32 requests going
+    through the device work queue (one persistent kernel) and the rest
+    through the slots: every request's outputs equal its lone launch."""
+    h = cm.Handle(0)
+    mix = serve.served_mix(24, rate_hz=1e6, seed=5, max_runs=20_000)
+    done = serve.run_mix(h, mix, budget_bytes=4 << 30, n_streams=4, queue=True)
+    assert len(done) == 24
+    for r in done:
+        alone = cm.run(r.w, handle=h)
+        for k in ("hist", "stats", "score", "best"):
+            if alone[k] is None:
+                continue
+            assert np.array_equal(r.result[k], alone[k]), (r.rid, k)
+    print(serve.latency_summary(done))
+
+
 def test_budget_smaller_than_mix_still_completes():
     h = cm.Handle(0)
     mix = serve.served_mix(16, rate_hz=1e6, seed=6, max_runs=10_000)
