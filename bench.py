@@ -65,12 +65,13 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "4bb05fcee0520618a8479d7e8448a0d57de623198c8cd944e2acb5b958a76618",
+TRAFFIC = {"sources_sha256": "350d1da93bae1b51b280031504c77dfccee8fb8885ea01beaeee3eb517947639",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block"
-           "bytes_per_launch": {"4,512": 2837504, "6,512": 2293760, "8,512": 1897472}}
+           "bytes_per_launch": {"4,512": 2838118, "6,512": 2294170, "8,512": 1897882}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
-                  "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp")
+                  "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp",
+                  "paper_2110_15425_amd/csrc/prep_score.hpp")
 
 
 def sources_hash():
