@@ -105,7 +105,15 @@ __host__ __device__ inline DensityGeo density_geo(uint32_t M) {
 
 namespace {
 
-__global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a) {
+// MAXT: workgroup size bound; REGD: diagonals per wavefront whose kernel
+// fragments stay in registers (at two wavefronts per SIMD a wavefront's 256
+// registers hold 24 diagonals' fragments beside the rest; measured on
+// MI355X at 1000 cells: 6 % faster than reading them from LDS every step.
+// One wavefront per tile with 48 diagonals in registers and the accumulator
+// as the new mass -- no partial sums, one barrier per step -- was 8 % slower
+// than reading everything from LDS, with one accumulation chain or two).
+template <int MAXT, int REGD>
+__global__ __launch_bounds__(MAXT) void ddm_density_kernel(DensityArgs a) {
   extern __shared__ double sh[];
   __shared__ double red[3][kMaxThreads / 64];
   __shared__ double wsum[3][kWin];
@@ -210,6 +218,15 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
   const int nd = dB >= dA ? dB - dA + 1 : 0;
   const int dS = dA + (nd * (int)grp) / (int)G, dE = dA + (nd * ((int)grp + 1)) / (int)G;
   const int l16 = lane & 15, l4 = lane >> 4;
+  // The kernel row does not change from step to step: the F_d fragments of
+  // this wavefront's first REGD diagonals stay in registers, so each step
+  // reads only their mass fragments from LDS.
+  const double* fa = f + (int)geo.FOFF + l16 - l4;
+  double Ar[REGD > 0 ? REGD : 1][4];
+#pragma unroll
+  for (int i = 0; i < REGD; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Ar[i][q] = dS + i < dE ? fa[16 * (dS + i) - 4 * q] : 0.0;
   double* cur = m0;
   double* nxt = m1;
   uint32_t n = 2;
@@ -218,17 +235,38 @@ __global__ __launch_bounds__(kMaxThreads) void ddm_density_kernel(DensityArgs a)
     // of the next diagonal are read while the current products run
     f64x4 C = {0.0, 0.0, 0.0, 0.0};
     if (tile < NT) {
-      const double* fa = f + (int)geo.FOFF + l16 - l4;
       const double* mb = cur + (c0 + l16 + nbi) * kBS + l4;
       double A[4], B[4];
       if (dS < dE) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          A[q] = fa[16 * dS - 4 * q];
-          B[q] = mb[4 * q - dS * kBS];
+        for (int q = 0; q < 4; ++q) B[q] = mb[4 * q - dS * kBS];
+      }
+      // two mass-fragment buffers in turn, so that the next diagonal's
+      // fragments are read while this diagonal's products run
+      double B1[4];
+#pragma unroll
+      for (int i = 0; i < REGD; ++i) {
+        const int d = dS + i;
+        if (d < dE) {
+          double* cu = (i & 1) ? B1 : B;
+          double* nx = (i & 1) ? B : B1;
+          const int dn = d + 1 < dE ? d + 1 : d;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) nx[q] = mb[4 * q - dn * kBS];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) C = __builtin_amdgcn_mfma_f64_16x16x4f64(Ar[i][q], cu[q], C, 0, 0, 0);
         }
       }
-      for (int d = dS; d < dE; ++d) {
+      if (REGD & 1) {  // the last register diagonal left the next fragments in B1
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[q] = B1[q];
+      }
+      const int dR = dS + REGD;  // the rest, fragments of both operands from LDS
+      if (dR < dE) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[q] = fa[16 * dR - 4 * q];
+      }
+      for (int d = dR; d < dE; ++d) {
         double An[4], Bn[4];
         const int dn = d + 1 < dE ? d + 1 : d;  // the last diagonal re-reads its own
 #pragma unroll
@@ -342,8 +380,12 @@ hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st) {
   const DensityGeo g = density_geo(a.cells);
   if (a.cells < 16u || g.W * 64u > (uint32_t)kMaxThreads || 2u * g.W * 64u < 256u * g.NT)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ddm_density_kernel, dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
-                     density_lds_bytes(a.cells), st, a);
+  if (g.W <= 8u)
+    hipLaunchKernelGGL((ddm_density_kernel<512, 24>), dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
+                       density_lds_bytes(a.cells), st, a);
+  else
+    hipLaunchKernelGGL((ddm_density_kernel<kMaxThreads, 0>), dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
+                       density_lds_bytes(a.cells), st, a);
   return hipGetLastError();
 }
 
