@@ -82,8 +82,11 @@ __device__ __forceinline__ int ceil_div16(int v) { return -floor_div16(-v); }
 }  // namespace
 
 // Launch geometry of M cells: NB blocks of 16 cells, NT output tiles of 16
-// blocks, G wavefronts per tile (W = NT G, 8 to 12; measured on MI355X at
-// 1000 cells: 2 per tile 5 % faster than 4, 1 per tile 25 % slower), the
+// blocks, G wavefronts per tile (W = NT G, 6 to 12; measured on MI355X at
+// 1000 cells, four tiles: with every fragment read from LDS, 2 per tile 5 %
+// faster than 4 and 1 per tile 25 % slower; with the kernel fragments of
+// the first diagonals in registers, 3 per tile (12 diagonals each) 2 %
+// faster than 2 (24 each) and 4 (6 each)), the
 // kernel row's offset
 // FOFF (entry of displacement 0) and width FW, and CB blocks per mass vector
 // (NB zero blocks on either side of the 16 NT output blocks).
@@ -95,7 +98,7 @@ __host__ __device__ inline DensityGeo density_geo(uint32_t M) {
   g.M = M;
   g.NB = (M + 15u) / 16u;
   g.NT = (g.NB + 15u) / 16u;
-  g.G = 8u / g.NT > 2u ? 8u / g.NT : 2u;
+  g.G = g.NT == 4u ? 3u : 8u / g.NT > 2u ? 8u / g.NT : 2u;
   g.W = g.NT * g.G;
   g.FOFF = 16u * g.NB + 16u;
   g.FW = 2u * g.FOFF + 1u;
@@ -107,8 +110,9 @@ namespace {
 
 // MAXT: workgroup size bound; REGD: diagonals per wavefront whose kernel
 // fragments stay in registers (at two wavefronts per SIMD a wavefront's 256
-// registers hold 24 diagonals' fragments beside the rest; measured on
-// MI355X at 1000 cells: 6 % faster than reading them from LDS every step.
+// registers hold 24 diagonals' fragments beside the rest, at three 12;
+// measured on MI355X at 1000 cells: 6 % faster than reading them from LDS
+// every step.
 // One wavefront per tile with 48 diagonals in registers and the accumulator
 // as the new mass -- no partial sums, one barrier per step -- was 8 % slower
 // than reading everything from LDS, with one accumulation chain or two).
@@ -380,7 +384,10 @@ hipError_t launch_ddm_density(const DensityArgs& a, hipStream_t st) {
   const DensityGeo g = density_geo(a.cells);
   if (a.cells < 16u || g.W * 64u > (uint32_t)kMaxThreads || 2u * g.W * 64u < 256u * g.NT)
     return hipErrorInvalidValue;
-  if (g.W <= 8u)
+  if (g.NT == 4u)
+    hipLaunchKernelGGL((ddm_density_kernel<768, 12>), dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
+                       density_lds_bytes(a.cells), st, a);
+  else if (g.W <= 8u)
     hipLaunchKernelGGL((ddm_density_kernel<512, 24>), dim3((uint32_t)a.n_settings), dim3(g.W * 64u),
                        density_lds_bytes(a.cells), st, a);
   else
