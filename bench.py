@@ -67,8 +67,8 @@ BATCH = 12
 # depends on it).
 TRAFFIC = {"sources_sha256": "350d1da93bae1b51b280031504c77dfccee8fb8885ea01beaeee3eb517947639",
            "batch": 12,
-           # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block"
-           "bytes_per_launch": {"4,512": 2838118, "6,512": 2294170, "8,512": 1897882}}
+           # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block,tail_sweeps"
+           "bytes_per_launch": {"4,512,0": 2838118, "6,512,0": 2294170, "8,512,0": 1897882}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp",
                   "paper_2110_15425_amd/csrc/prep_score.hpp")
@@ -190,10 +190,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy five times (the reference "
                          "kernel that scales the profiler's FETCH_SIZE/WRITE_SIZE counters)")
-    ap.add_argument("--shape", default=None, metavar="RPL,SPS[,BLOCK[,WAVES]]",
+    ap.add_argument("--shape", default=None, metavar="RPL,SPS[,BLOCK[,WAVES[,TAIL]]]",
                     help="use this runs_per_lane,steps_per_sync (and workgroup size, register "
-                         "cap) for the batched launch instead of tuning it (so that separate "
-                         "profiler runs see the same kernel)")
+                         "cap, trailing sweeps in half-size chunks) for the batched launch "
+                         "instead of tuning it (so that separate profiler runs see the same "
+                         "kernel)")
     return ap.parse_args()
 
 
@@ -387,7 +388,8 @@ def main():
         rpl, sps, *rest = (int(v) for v in args.shape.split(","))
         h_tuned.set_tuning(W.LCA, W.FP32_STEP, runs_per_lane=rpl, steps_per_sync=sps,
                            block=rest[0] if rest else 256,
-                           waves_per_simd=rest[1] if len(rest) > 1 else 0)
+                           waves_per_simd=rest[1] if len(rest) > 1 else 0,
+                           tail_sweeps=rest[2] if len(rest) > 2 else 0)
         tuned = h_tuned.get_tuning(W.LCA, W.FP32_STEP)
     else:
         tuned, _, _ = autotune.tune(h_tuned, wb, reps=2,
@@ -433,7 +435,8 @@ def main():
     kern_rate = head["run_steps"] / (head["kern_ms"] / 1e3)
     traffic = None
     if TRAFFIC["sources_sha256"] == sources_hash() and TRAFFIC["batch"] == BATCH:
-        traffic = TRAFFIC["bytes_per_launch"].get(f"{tuned['runs_per_lane']},{tuned['block']}")
+        traffic = TRAFFIC["bytes_per_launch"].get(
+            f"{tuned['runs_per_lane']},{tuned['block']},{tuned.get('tail_sweeps', 0)}")
     line = {
         "metric": "run-timesteps/sec on 1 MI355X (FP32 batched vs FP64 plain)",
         "value": head["rate"],

@@ -200,9 +200,17 @@ typedef struct {
  *                 paper's GPU kernels (Sec. 6.3); a cap below the kernel's
  *                 own use spills or recomputes values.  Other values:
  *                 CM_E_UNSUPPORTED.  The time-course variant ignores it.
+ *  tail_sweeps    DDM and conflict LCA, one lane per run: the last
+ *                 tail_sweeps sweeps of a launch (cm_launch's one sweep
+ *                 included) take chunks of half the runs -- twice as many
+ *                 workgroups, each half as long -- so that the launch's
+ *                 last workgroups end closer together (0..12; 0: none).
+ *                 Other kinds: 0 only (else CM_E_UNSUPPORTED).  The
+ *                 time-course variant ignores it.
  * Results do not depend on these choices. */
 typedef struct {
   uint32_t block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run, waves_per_simd;
+  uint32_t tail_sweeps;
 } cm_tuning;
 
 /* Pure host checks of a model/sweep pair (the rules above and the kind's

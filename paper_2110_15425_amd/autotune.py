@@ -6,10 +6,11 @@ The knobs are the ones in ``cm_tuning``: runs handed to a workgroup per lane
 (which trades occupancy against the tail of long runs), steps between
 refills of finished lanes (which trades idle lanes against refill cost) and,
 for the lane kernels, the workgroup size (how many unfinished runs one
-workgroup packs together while its chunk drains) and the register cap that
+workgroup packs together while its chunk drains), the register cap that
 sets how many wavefronts fit per SIMD (the register use versus occupancy
 trade-off of the paper's GPU kernels: more wavefronts hide more latency, but
-a cap below the kernel's own register use spills).
+a cap below the kernel's own register use spills) and, for batched
+launches, half-size chunks for the last sweeps (a shorter launch tail).
 Results can be persisted in a JSON cache keyed by device, kind, precision
 and a size class of the sweep, so a later process reuses them without
 re-timing.
@@ -28,6 +29,7 @@ STEPS_PER_SYNC = (2, 4, 8, 12, 16, 32)
 RUNS_PER_WAVE = (1, 2, 4, 8, 16, 32, 64)  # DDM, one wavefront per run
 WAVES_PER_SIMD = (0, 4, 8)  # 0: the compiler's register allocation
 BLOCKS = (256, 512, 1024)  # threads per workgroup of the lane kernels
+TAIL_SWEEPS = (0, 2, 4)  # batched launches: trailing sweeps in half-size chunks
 
 
 def size_class(w):
@@ -73,10 +75,12 @@ def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=
     """Time every candidate shape on workload ``w`` (a workload dict, or a list
     of workloads of one kind and precision timed as one batched launch);
     install and return the best as (tuning dict, kernel ms, table).  Table
-    rows are (rpl, sps, lpr, ms, waves cap, block): first every candidate
-    shape in 256-thread workgroups, then, for the lane kernels, the best
-    shape in workgroups of 512 and 1024 threads (with as many and with half
-    as many runs per lane), then the register caps on the best of those.
+    rows are (rpl, sps, lpr, ms, waves cap, block, tail sweeps): first every
+    candidate shape in 256-thread workgroups, then, for the lane kernels,
+    the best shape in workgroups of 512 and 1024 threads (with as many and
+    with half as many runs per lane), then the register caps on the best of
+    those, then -- for a batched launch -- half-size chunks for its last
+    sweeps.
     Shapes within a few per cent of each other are not told apart by one
     timing, so the ``finalists`` fastest are timed ``rounds`` more times and
     ranked by their fastest timing."""
@@ -87,32 +91,32 @@ def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=
     table = []
     cands = candidates or default_candidates(w)
 
-    def run(rpl, sps, lpr, waves=0, block=256, best_of=1):
+    def run(rpl, sps, lpr, waves=0, block=256, best_of=1, tail=0):
         handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr,
-                          waves_per_simd=waves, block=block)
+                          waves_per_simd=waves, block=block, tail_sweeps=tail)
         return min(time_shape(handle, ds, reps) for _ in range(best_of))
 
     for c in cands:
         rpl, sps = c[0], c[1]
         lpr = c[2] if len(c) > 2 else 1
         ms = run(rpl, sps, lpr)
-        table.append((rpl, sps, lpr, ms, 0, 256))
+        table.append((rpl, sps, lpr, ms, 0, 256, 0))
         if verbose:
             print(f"  runs/lane {rpl:3d} steps/sync {sps:3d} lanes/run {lpr:2d}: {ms:.4f} ms",
                   flush=True)
     table.sort(key=lambda r: r[3])
-    for i, (rpl, sps, lpr, ms, _, _) in enumerate(table[:finalists]):
+    for i, (rpl, sps, lpr, ms, _, _, _) in enumerate(table[:finalists]):
         ms = min(ms, run(rpl, sps, lpr, best_of=rounds))
-        table[i] = (rpl, sps, lpr, ms, 0, 256)
+        table[i] = (rpl, sps, lpr, ms, 0, 256, 0)
     best = min(table, key=lambda r: r[3])
-    rpl, sps, lpr, ms, _, _ = best
+    rpl, sps, lpr, ms, _, _, _ = best
     if kind in (0, 1) and lpr != 64:
         # workgroup size: a larger workgroup packs more unfinished runs
         # together while its chunk drains, but holds more of a compute unit
         for blk in BLOCKS[1:]:
             for r in sorted({rpl, max(1, rpl // 2)}):
                 t = run(r, sps, lpr, block=blk, best_of=rounds)
-                table.append((r, sps, lpr, t, 0, blk))
+                table.append((r, sps, lpr, t, 0, blk, 0))
                 if verbose:
                     print(f"  block {blk} runs/lane {r}: {t:.4f} ms", flush=True)
         best = min(table, key=lambda r: r[3])
@@ -120,13 +124,23 @@ def tune(handle, w, reps=3, candidates=None, verbose=False, finalists=4, rounds=
         # wavefronts per SIMD against the compiler's own allocation
         for wv in WAVES_PER_SIMD[1:]:
             t = run(best[0], sps, lpr, waves=wv, block=best[5], best_of=rounds)
-            table.append((best[0], sps, lpr, t, wv, best[5]))
+            table.append((best[0], sps, lpr, t, wv, best[5], 0))
             if verbose:
                 print(f"  waves/SIMD cap {wv}: {t:.4f} ms", flush=True)
         best = min(table, key=lambda r: r[3])
-    rpl, sps, lpr, ms, waves, block = best
+        if len(ws) > 1:
+            # the launch's tail: its last workgroups, ending at scattered
+            # times, leave compute units idle; half-size chunks for the last
+            # sweeps make those workgroups shorter
+            for tl in TAIL_SWEEPS[1:]:
+                t = run(best[0], sps, lpr, waves=best[4], block=best[5], best_of=rounds, tail=tl)
+                table.append((best[0], sps, lpr, t, best[4], best[5], tl))
+                if verbose:
+                    print(f"  tail sweeps {tl}: {t:.4f} ms", flush=True)
+            best = min(table, key=lambda r: r[3])
+    rpl, sps, lpr, ms, waves, block, tail = best
     handle.set_tuning(kind, prec, runs_per_lane=rpl, steps_per_sync=sps, lanes_per_run=lpr,
-                      waves_per_simd=waves, block=block)
+                      waves_per_simd=waves, block=block, tail_sweeps=tail)
     return handle.get_tuning(kind, prec), ms, table
 
 

@@ -62,7 +62,8 @@ class Result(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_uint32), ("runs_per_lane", C.c_uint32),
                 ("steps_per_sync", C.c_uint32), ("tile_rows", C.c_uint32),
-                ("lanes_per_run", C.c_uint32), ("waves_per_simd", C.c_uint32)]
+                ("lanes_per_run", C.c_uint32), ("waves_per_simd", C.c_uint32),
+                ("tail_sweeps", C.c_uint32)]
 
 
 class HostResult(C.Structure):
@@ -197,8 +198,9 @@ class Handle:
         return float(ms.value), int(n.value)
 
     def set_tuning(self, kind, precision, block=0, runs_per_lane=0, steps_per_sync=0,
-                   tile_rows=0, lanes_per_run=0, waves_per_simd=0):
-        t = Tuning(block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run, waves_per_simd)
+                   tile_rows=0, lanes_per_run=0, waves_per_simd=0, tail_sweeps=0):
+        t = Tuning(block, runs_per_lane, steps_per_sync, tile_rows, lanes_per_run, waves_per_simd,
+                   tail_sweeps)
         check(lib().cm_set_tuning(self.h, int(kind), int(precision), C.byref(t)))
 
     def get_tuning(self, kind, precision):
@@ -206,7 +208,8 @@ class Handle:
         check(lib().cm_get_tuning(self.h, int(kind), int(precision), C.byref(t)))
         return dict(block=t.block, runs_per_lane=t.runs_per_lane,
                     steps_per_sync=t.steps_per_sync, tile_rows=t.tile_rows,
-                    lanes_per_run=t.lanes_per_run, waves_per_simd=t.waves_per_simd)
+                    lanes_per_run=t.lanes_per_run, waves_per_simd=t.waves_per_simd,
+                    tail_sweeps=t.tail_sweeps)
 
 
 class DeviceSweep:

@@ -757,6 +757,17 @@ cm_status launch_lane_group(cm_handle* h, uint32_t kind, uint32_t prec, const cm
     cm_status st =
         plan_lane(h, &ms[i], &ss[i], &rs[i], (char*)wss[i], Ls[i], scan_block, launch_runs, tc, b.a[k], groups, l);
     if (st != CM_OK) return st;
+    // the launch's last tail_sweeps sweeps: chunks of half the runs, so
+    // that the last workgroups of the launch end closer together (the
+    // window of the smaller chunk is no wider, so the LDS plan holds)
+    const cm_tuning& tu = h->tune[kind][prec];
+    if (!scan && !tc.every && k + tu.tail_sweeps >= n && !b.a[k].direct && b.a[k].chunk >= 2u) {
+      cm::SimArgs& sa = b.a[k];
+      const uint64_t runs = ss[i].n_settings * ss[i].trials;
+      sa.chunk = (sa.chunk + 1u) / 2u;
+      sa.window = (uint32_t)std::min<uint64_t>((sa.chunk - 1u) / sa.trials + 2u, sa.n_settings);
+      groups = (runs + sa.chunk - 1u) / sa.chunk;
+    }
     b.base[k] = base;
     base += groups;
     lds = std::max(lds, l);
@@ -977,6 +988,9 @@ cm_status cm_set_tuning(cm_handle* h, uint32_t kind, uint32_t precision, const c
     return fail(CM_E_UNSUPPORTED, "waves_per_simd must be 0, 4 or 8");
   if (v.waves_per_simd && kind != CM_DDM && kind != CM_CONFLICT_LCA)
     return fail(CM_E_UNSUPPORTED, "waves_per_simd applies to the DDM and conflict-LCA lane kernels");
+  if (v.tail_sweeps > cm::kMaxBatch) return fail(CM_E_INVALID, "tail_sweeps must be <= %u", cm::kMaxBatch);
+  if (v.tail_sweeps && kind != CM_DDM && kind != CM_CONFLICT_LCA)
+    return fail(CM_E_UNSUPPORTED, "tail_sweeps applies to the DDM and conflict-LCA lane kernels");
   h->tune[kind][precision] = v;
   return ok();
 }
@@ -1155,6 +1169,7 @@ std::vector<uint64_t> graph_signature(const cm_handle* h, uint32_t n, const cm_m
       put(((uint64_t)t.block << 32) | t.runs_per_lane);
       put(((uint64_t)t.steps_per_sync << 32) | t.tile_rows);
       put(((uint64_t)t.lanes_per_run << 32) | t.waves_per_simd);
+      put(t.tail_sweeps);
     }
   put(n);
   for (uint32_t i = 0; i < n; ++i) {

@@ -31,10 +31,10 @@ def test_every_side_workload_is_a_valid_sweep():
 def test_traffic_table_shape():
     t = bench.TRAFFIC
     assert len(t["sources_sha256"]) == 64 and t["batch"] == bench.BATCH
-    # keyed "runs_per_lane,block" of the profiled launch shape
+    # keyed "runs_per_lane,block,tail_sweeps" of the profiled launch shape
     for k, v in t["bytes_per_launch"].items():
-        rpl, block = (int(x) for x in k.split(","))
-        assert rpl >= 1 and block in (256, 512, 1024) and v > 0, k
+        rpl, block, tail = (int(x) for x in k.split(","))
+        assert rpl >= 1 and block in (256, 512, 1024) and 0 <= tail <= bench.BATCH and v > 0, k
     for f in bench.KERNEL_SOURCES:
         assert os.path.exists(os.path.join(ROOT, f)), f
 

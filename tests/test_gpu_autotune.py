@@ -18,9 +18,10 @@ def test_tune_installs_the_fastest_listed_shape():
     w = W.conflict(trials=400, precision=W.FP32_STEP)
     before = cm.run(w, handle=h)
     t, ms, table = autotune.tune(h, w, reps=2, candidates=CANDS, finalists=2, rounds=2)
-    assert all(len(r) == 6 for r in table)
+    assert all(len(r) == 7 for r in table)
+    assert all(r[6] == 0 for r in table)  # one sweep: no tail axis
     shapes = table[:len(CANDS)]
-    assert all(r[4:] == (0, 256) for r in shapes)
+    assert all(r[4:6] == (0, 256) for r in shapes)
     assert {(r[0], r[1]) for r in shapes} == set(CANDS)
     best = min(shapes, key=lambda r: r[3])
     # the workgroup-size axis on the best shape, with its runs per lane and half
@@ -50,6 +51,41 @@ def test_tune_a_batch():
     assert (t["runs_per_lane"], t["steps_per_sync"], t["lanes_per_run"]) in \
         {(2, 8, 1), (4, 8, 64)}
     assert ms > 0
+    ws = [W.conflict(trials=2000, seed=s, grid=W.control_grid(4), precision=W.FP32_STEP) for s in (1, 2, 3)]
+    t, ms, table = autotune.tune(h, ws, reps=2, candidates=[(2, 8)], finalists=1, rounds=1)
+    tails = [r for r in table if r[6] != 0]  # a batch: the tail axis on the best shape
+    assert [r[6] for r in tails] == [2, 4]
+    assert t["tail_sweeps"] == min(table, key=lambda r: r[3])[6]
+
+
+def test_tail_sweeps_leave_results_unchanged():
+    """Half-size chunks for the last sweeps of a batched launch (and for
+    cm_launch's one sweep) change only how runs are split among workgroups:
+    every run's outcome, the histograms and the scores stay the same."""
+    h = cm.Handle(0)
+    ws = [W.conflict(trials=1500, seed=s, grid=W.control_grid(5), reward=1.0, cost=0.1,
+                     precision=W.FP32_STEP) for s in (4, 5, 6)]
+    ws.append(W.ddm(trials=3000, seed=7, drifts=np.linspace(0.0, 0.4, 3), precision=W.FP32_STEP))
+    outs = []
+    for tail in (0, 2, 12):
+        h.set_tuning(W.LCA, W.FP32_STEP, tail_sweeps=tail, runs_per_lane=4)
+        h.set_tuning(W.DDM, W.FP32_STEP, tail_sweeps=tail, lanes_per_run=1, runs_per_lane=3)
+        assert h.get_tuning(W.LCA, W.FP32_STEP)["tail_sweeps"] == tail
+        ds = [cm.DeviceSweep(h, w, dumps=True) for w in ws]
+        cm.launch_batch(h, ds)
+        outs.append([d.results() for d in ds] + [cm.run(ws[0], dumps=True, handle=h)])
+    for o in outs[1:]:
+        for i, (x, y) in enumerate(zip(outs[0], o)):
+            for k in ("hist", "stats", "score", "best", "run_choice", "run_step", "run_flag", "run_state"):
+                if x.get(k) is not None or y.get(k) is not None:
+                    assert np.array_equal(x[k], y[k]), (i, k)
+    for bad, st in ((dict(tail_sweeps=13), cm.E_INVALID),):
+        with pytest.raises(cm.CmError) as e:
+            h.set_tuning(W.LCA, W.FP32_STEP, **bad)
+        assert e.value.status == st
+    with pytest.raises(cm.CmError) as e:
+        h.set_tuning(W.RNN, W.BF16_PROJ, tail_sweeps=2)
+    assert e.value.status == cm.E_UNSUPPORTED
 
 
 def test_tuned_handle_cache_round_trip(tmp_path):
