@@ -68,7 +68,9 @@ BATCH = 12
 TRAFFIC = {"sources_sha256": "350d1da93bae1b51b280031504c77dfccee8fb8885ea01beaeee3eb517947639",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block,tail_sweeps"
-           "bytes_per_launch": {"4,512,0": 2838118, "6,512,0": 2294170, "8,512,0": 1897882}}
+           "bytes_per_launch": {"4,512,0": 2838118, "6,512,0": 2294170, "8,512,0": 1897882,
+                                "4,512,2": 3067904, "4,512,4": 3297690, "6,512,2": 2464154,
+                                "6,512,4": 2637210, "8,512,2": 2054144, "8,512,4": 2211430}}
 KERNEL_SOURCES = ("paper_2110_15425_amd/csrc/sim_lane.hip", "paper_2110_15425_amd/csrc/rng.hpp",
                   "paper_2110_15425_amd/csrc/lca_step.hpp", "paper_2110_15425_amd/csrc/internal.hpp",
                   "paper_2110_15425_amd/csrc/prep_score.hpp")
