@@ -458,8 +458,14 @@ cm_status cm_poll(cm_handle *h, uint64_t ticket, int *done);
  *                   sweep, its scores) are complete, and its host copies
  *                   with them; the ticket is then retired.  It never waits.
  *                   CM_E_INVALID for an unknown ticket.
- *  cm_queue_destroy asks the kernel to stop, waits for it and frees the
- *                   queue; unfinished requests are abandoned. */
+ *  cm_queue_destroy asks the kernel to stop, waits until it has ended and
+ *                   frees the queue.  A running kernel first finishes the
+ *                   items already copied to the device; requests that
+ *                   cm_queue_poll has not reported done are abandoned
+ *                   (their outputs may be incomplete; their tickets are
+ *                   void), and their buffers must stay allocated until
+ *                   cm_queue_destroy returns.
+ * A queue is not thread-safe: submit, poll and destroy from one thread. */
 typedef struct cm_queue cm_queue;
 cm_status cm_queue_create(cm_handle *h, uint32_t kind, uint32_t precision, uint32_t slots,
                           uint32_t groups_per_cu, uint32_t idle_us, cm_queue **out);

@@ -74,6 +74,7 @@ struct cm_queue {
   size_t o_dring = 0, o_ddesc = 0;
   hipStream_t run = nullptr;
   hipEvent_t run_done = nullptr;
+  hipEvent_t handoff = nullptr;  // the producer stream's work before a submit
   bool launched = false;
   uint32_t published = 0;  // requests published (== *tail)
   uint64_t next_ticket = 1;
@@ -1318,6 +1319,7 @@ void queue_free(cm_queue* q) {
     (void)hipStreamDestroy(q->run);
   }
   if (q->run_done) (void)hipEventDestroy(q->run_done);
+  if (q->handoff) (void)hipEventDestroy(q->handoff);
   if (q->copy) {
     (void)hipStreamSynchronize(q->copy);
     (void)hipStreamDestroy(q->copy);
@@ -1377,6 +1379,7 @@ cm_status cm_queue_create(cm_handle* h, uint32_t kind, uint32_t precision, uint3
   if ((e = hipMalloc((void**)&q->dev, dbytes)) != hipSuccess || (e = hipMemset(q->dev, 0, dbytes)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&q->run, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&q->run_done, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&q->handoff, hipEventDisableTiming)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&q->copy, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     queue_free(q);
@@ -1453,12 +1456,9 @@ cm_status cm_queue_submit(cm_queue* q, const cm_model* m, const cm_sweep* s, con
   // item can run
   hipError_t e;
   if (producer_stream) {
-    hipEvent_t ev;
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-    e = hipEventRecord(ev, (hipStream_t)producer_stream);
-    if (e == hipSuccess) e = hipEventSynchronize(ev);
-    (void)hipEventDestroy(ev);
-    if (e != hipSuccess) return hip_fail(e, "producer hand-off");
+    if ((e = hipEventRecord(q->handoff, (hipStream_t)producer_stream)) != hipSuccess ||
+        (e = hipEventSynchronize(q->handoff)) != hipSuccess)
+      return hip_fail(e, "producer hand-off");
   }
   const uint64_t t = q->next_ticket++;
   cm::QueueDesc& d = q->desc[slot];

@@ -204,3 +204,25 @@ def test_queue_host_copies():
         assert e.value.status == cm.E_INVALID
     finally:
         q.close()
+
+
+def test_queue_destroy_with_requests_in_flight():
+    """Destroying a queue whose requests were never polled ends its kernel
+    and returns; a new queue on the same handle then works as before."""
+    h = cm.Handle(0)
+    w = W.conflict(trials=3000, seed=71, grid=W.control_grid(4), precision=W.FP32_STEP)
+    ds = [cm.DeviceSweep(h, W.with_(w, seed=71 + i)) for i in range(3)]
+    q = cm.DeviceQueue(h, W.LCA, W.FP32_STEP, slots=4, idle_us=20000)
+    for d in ds:
+        q.submit(d)
+    print("queue: destroy with 3 requests in flight", flush=True)
+    t0 = time.time()
+    q.close()
+    assert time.time() - t0 < 30.0
+    q2 = cm.DeviceQueue(h, W.LCA, W.FP32_STEP, slots=4, idle_us=20000)
+    try:
+        d = cm.DeviceSweep(h, w)
+        _wait(q2, [q2.submit(d)])
+        _same(d.results(), cm.run(w, handle=h), "after a destroy")
+    finally:
+        q2.close()
