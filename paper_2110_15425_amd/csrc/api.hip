@@ -55,9 +55,10 @@ static void clear_graphs(cm_handle* h) {
 }
 
 // The device work queue: pinned host memory the host publishes into
-// (header, done words, item ring, request descriptors), device counters the
-// persistent kernel claims and counts with, and the host's view of the
-// requests in flight.
+// (header, done words, request ring, request descriptors), device memory the
+// persistent kernel claims and counts with (claim word, copy count, pull
+// lock, per-slot counters, copies of the ring and descriptors), and the
+// host's view of the requests in flight.
 struct cm_queue {
   cm_handle* h = nullptr;
   uint32_t kind = 0, prec = 0, cap_slots = 0, cap_ring = 0, groups = 0;
