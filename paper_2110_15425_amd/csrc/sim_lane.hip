@@ -728,12 +728,20 @@ __global__ __launch_bounds__(kBlock) void queue_kernel(QueueArgs q) {
         const uint32_t r = (uint32_t)(w >> 32), c = (uint32_t)w;
         const uint32_t dt = __hip_atomic_load(q.dev_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (r < dt) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the copies made before dev_tail passed r
           // An entry whose number is not r was replaced by a later request,
           // which the host publishes only once r is done: r has no items left.
-          const unsigned long long ni =
-              __hip_atomic_load(&q.dring[r % q.cap_ring].num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((uint32_t)(ni >> 32) == r && c < (uint32_t)ni) {
+          // A first look without a fence (an idle workgroup looks at the last,
+          // exhausted request over and over); a fence and a second look
+          // before acting on it.
+          const QueueReq* e = q.dring + r % q.cap_ring;
+          unsigned long long ni = __hip_atomic_load(&e->num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bool left = (uint32_t)(ni >> 32) == r && c < (uint32_t)ni;
+          if (left || r + 1u < dt) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the copies made before dev_tail passed r
+            ni = __hip_atomic_load(&e->num_items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            left = (uint32_t)(ni >> 32) == r && c < (uint32_t)ni;
+          }
+          if (left) {
             const unsigned long long v = __hip_atomic_fetch_add(q.word, 1ull, __ATOMIC_ACQUIRE,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t r2 = (uint32_t)(v >> 32), c2 = (uint32_t)v;
