@@ -278,8 +278,10 @@ def serving(cm, seconds, queue=False):
     h = cm.Handle(0)
     warm = serve.served_mix(8, rate_hz=1e6, seed=12, max_runs=10_000)
     serve.run_mix(h, warm, queue=queue)
-    done = serve.run_mix(h, mix, budget_bytes=32 << 30, n_streams=4, queue=queue)
-    steps = sum(cm.run_steps(r.w, r.result) for r in done)
+    steps_of = {}  # run-steps per request, taken as it finishes (its results are then released)
+    done = serve.run_mix(h, mix, budget_bytes=32 << 30, n_streams=4, queue=queue,
+                         on_done=lambda r: steps_of.__setitem__(r.rid, cm.run_steps(r.w, r.result)))
+    steps = sum(steps_of.values())
     t0 = min(r.arrival for r in done)
     t1 = max(r.done for r in done)
     summ = serve.latency_summary(done)
