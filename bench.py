@@ -65,7 +65,7 @@ BATCH = 12
 # valid only for the kernel sources it was measured on, and given per
 # runs-per-lane (the number of workgroup flushes, hence the write traffic,
 # depends on it).
-TRAFFIC = {"sources_sha256": "ab82c69f977ff227fb4a529578fe2265a9cfe45f8fa28e908cf74e073bd43b84",
+TRAFFIC = {"sources_sha256": "eca0a96cb1cf47354afe1979d186ac3cf493f8d02cd39c4da3186237b32dfea4",
            "batch": 12,
            # profiles/sim_lane_lca_fp32_conflict_batched.md; key "runs_per_lane,block,tail_sweeps"
            "bytes_per_launch": {"4,512,0": 2838118, "6,512,0": 2294170, "8,512,0": 1897882,

@@ -130,7 +130,7 @@ struct ScoreBatch {
 // items with one fetch-and-add on a 64-bit word holding (request index, next
 // item); the word moves to the next request by compare-and-swap only once
 // every item of the current one is claimed.
-constexpr uint64_t kQueuePrepSpan = 1u << 16;  // preparation indices per piece
+constexpr uint64_t kQueuePrepSpan = 1u << 12;  // preparation indices per piece
 struct QueueReq {
   // (publication number << 32) | item count, read and written as one word:
   // the number tells a stale entry from the one that replaced it
