@@ -226,3 +226,23 @@ def test_queue_destroy_with_requests_in_flight():
         _same(d.results(), cm.run(w, handle=h), "after a destroy")
     finally:
         q2.close()
+
+
+def test_queue_large_grid_few_trials():
+    """A 4,000-setting grid of 2 trials each (outcomes counted straight into
+    global memory, many preparation pieces, the score and argmax over the
+    whole grid in one workgroup) and a 2,000 x 50 scored grid, each equal to
+    cm_launch's."""
+    h = cm.Handle(0)
+    g = W.control_grid(64)
+    ws = [W.conflict(trials=2, seed=81, grid=g[:4000], reward=1.0, cost=0.1, precision=W.FP32_STEP),
+          W.conflict(trials=50, seed=82, grid=g[:2000], reward=1.0, cost=0.1, precision=W.FP32_STEP)]
+    q = cm.DeviceQueue(h, W.LCA, W.FP32_STEP, slots=4, idle_us=20000)
+    try:
+        ds = [cm.DeviceSweep(h, w, dumps=True) for w in ws]
+        print("queue: large grids", flush=True)
+        _wait(q, [q.submit(d) for d in ds])
+        for i, (w, d) in enumerate(zip(ws, ds)):
+            _same(d.results(), cm.run(w, dumps=True, handle=h), f"grid {i}")
+    finally:
+        q.close()
