@@ -41,7 +41,9 @@
 extern "C" {
 #endif
 
-#define CM_ABI_VERSION 1u
+/* cm_model.abi_version must equal this.  2: cm_tuning gained tail_sweeps
+ * and the cm_queue_* device work queue was added. */
+#define CM_ABI_VERSION 2u
 
 typedef struct cm_handle cm_handle;
 

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, E_INVALID, E_BUDGET, E_DEVICE, E_UNSUPPORTED, E_BUSY = range(6)
 STATUS_NAMES = {0: "CM_OK", 1: "CM_E_INVALID", 2: "CM_E_BUDGET", 3: "CM_E_DEVICE",
                 4: "CM_E_UNSUPPORTED", 5: "CM_E_BUSY"}
